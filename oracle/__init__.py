@@ -1,0 +1,221 @@
+"""CPU oracle for the stereo / scene-flow hot path (ctypes over liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  The
+C sources (sgm_oracle.c, lrnet_oracle.c) are plain single-threaded loops that
+follow the definitions one by one; this module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRCS = ["sgm_oracle.c", "lrnet_oracle.c"]
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, no FMA contraction, one thread."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           "-o", tmp] + [os.path.join(_HERE, s) for s in _SRCS] + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        _lib = ct.CDLL(_SO)
+        _declare(_lib)
+    return _lib
+
+
+P = ct.c_void_p
+I = ct.c_int
+F = ct.c_float
+
+
+def _declare(L):
+    L.oracle_census.argtypes = [P, I, I, I, P]
+    L.oracle_cost.argtypes = [P, P, I, I, I, I, P]
+    L.oracle_path_cost.argtypes = [P, I, I, I, I, I, I, P]
+    L.oracle_aggregate.argtypes = [P, I, I, I, I, I, ct.c_uint, P]
+    L.oracle_wta.argtypes = [P, I, I, I, P, P]
+    L.oracle_lr_check.argtypes = [P, P, P, I, I, I, P, P]
+    L.oracle_no_check.argtypes = [P, I, I, P, P]
+    L.oracle_combine.argtypes = [P, P, P, P, P, I, I, I, F, F, F, F, P, P, P, P]
+    L.oracle_disparity.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, P, P, P]
+    L.oracle_features.argtypes = [P, I, P, P, I, I, I, I, P]
+    L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
+    L.oracle_lrnet.restype = ct.c_double
+    L.oracle_lrnet_nparams.restype = I
+    L.oracle_bf16.argtypes = [F]
+    L.oracle_bf16.restype = F
+    L.oracle_adam.argtypes = [P, P, P, P, I, F, F, F, F, F, F]
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def census(img: np.ndarray) -> np.ndarray:
+    img = np.ascontiguousarray(img, np.uint8)
+    H, W = img.shape
+    out = np.zeros((H, W), np.uint64)
+    lib().oracle_census(_p(img), H, W, W, _p(out))
+    return out
+
+
+def cost(cen_base, cen_match, D: int, base_is_right: bool) -> np.ndarray:
+    cb = np.ascontiguousarray(cen_base, np.uint64)
+    cm = np.ascontiguousarray(cen_match, np.uint64)
+    H, W = cb.shape
+    out = np.zeros((H, W, D), np.uint8)
+    lib().oracle_cost(_p(cb), _p(cm), H, W, D, int(base_is_right), _p(out))
+    return out
+
+
+def path_cost(cost_vol: np.ndarray, P1: int, P2: int, direction: int) -> np.ndarray:
+    c = np.ascontiguousarray(cost_vol, np.uint8)
+    H, W, D = c.shape
+    out = np.zeros((H, W, D), np.int32)
+    lib().oracle_path_cost(_p(c), H, W, D, P1, P2, direction, _p(out))
+    return out
+
+
+def aggregate(cost_vol: np.ndarray, P1: int, P2: int, path_mask: int = 0xFF) -> np.ndarray:
+    c = np.ascontiguousarray(cost_vol, np.uint8)
+    H, W, D = c.shape
+    out = np.zeros((H, W, D), np.uint16)
+    lib().oracle_aggregate(_p(c), H, W, D, P1, P2, path_mask, _p(out))
+    return out
+
+
+def wta(S: np.ndarray):
+    S = np.ascontiguousarray(S, np.uint16)
+    H, W, D = S.shape
+    w = np.zeros((H, W), np.int16)
+    ds = np.zeros((H, W), np.float32)
+    lib().oracle_wta(_p(S), H, W, D, _p(w), _p(ds))
+    return w, ds
+
+
+def lr_check(wta_l, wta_r, dsub_l, tol: int = 1):
+    wl = np.ascontiguousarray(wta_l, np.int16)
+    wr = np.ascontiguousarray(wta_r, np.int16)
+    ds = np.ascontiguousarray(dsub_l, np.float32)
+    H, W = wl.shape
+    valid = np.zeros((H, W), np.uint8)
+    disp = np.zeros((H, W), np.float32)
+    lib().oracle_lr_check(_p(wl), _p(wr), _p(ds), H, W, tol, _p(valid), _p(disp))
+    return valid, disp
+
+
+def no_check(dsub_l):
+    ds = np.ascontiguousarray(dsub_l, np.float32)
+    H, W = ds.shape
+    valid = np.zeros((H, W), np.uint8)
+    disp = np.zeros((H, W), np.float32)
+    lib().oracle_no_check(_p(ds), H, W, _p(valid), _p(disp))
+    return valid, disp
+
+
+def combine(disp0, valid0, disp1, valid1, flow, cam=None):
+    d0 = np.ascontiguousarray(disp0, np.float32)
+    v0 = np.ascontiguousarray(valid0, np.uint8)
+    d1 = np.ascontiguousarray(disp1, np.float32)
+    v1 = np.ascontiguousarray(valid1, np.uint8)
+    fl = np.ascontiguousarray(flow, np.float32)
+    H, W = d0.shape
+    sf4 = np.zeros((H, W, 4), np.float32)
+    valid = np.zeros((H, W), np.uint8)
+    xyz0 = np.zeros((H, W, 3), np.float32)
+    motion = np.zeros((H, W, 3), np.float32)
+    if cam is None:
+        has, f, B, cx, cy = 0, 0.0, 0.0, 0.0, 0.0
+    else:
+        has = 1
+        f, B, cx, cy = cam
+    lib().oracle_combine(_p(d0), _p(v0), _p(d1), _p(v1), _p(fl), H, W, has, f, B, cx, cy,
+                         _p(sf4), _p(valid), _p(xyz0), _p(motion))
+    if cam is None:
+        return sf4, valid
+    return sf4, valid, xyz0, motion
+
+
+def disparity(left, right, D, P1=10, P2=120, path_mask=0xFF, tol=1):
+    """Full plain disparity map of one pair (census, both views, LR check)."""
+    L = np.ascontiguousarray(left, np.uint8)
+    R = np.ascontiguousarray(right, np.uint8)
+    H, W = L.shape
+    w = np.zeros((H, W), np.int16)
+    disp = np.zeros((H, W), np.float32)
+    valid = np.zeros((H, W), np.uint8)
+    lib().oracle_disparity(_p(L), _p(R), H, W, W, D, P1, P2, path_mask, tol, _p(w), _p(disp),
+                           _p(valid))
+    return w, disp, valid
+
+
+def features(img, S, wta_map, P2: int = 120):
+    img = np.ascontiguousarray(img, np.uint8)
+    S = np.ascontiguousarray(S, np.uint16)
+    w = np.ascontiguousarray(wta_map, np.int16)
+    H, W, D = S.shape
+    feat = np.zeros((H, W, 4), np.float32)
+    lib().oracle_features(_p(img), W, _p(S), _p(w), H, W, D, P2, _p(feat))
+    return feat
+
+
+NPARAM = 5377
+
+
+def lrnet(feat, params, label=None, round_bf16=True, want_grad=False):
+    """Forward (and backward) of the 4-layer network over a batch.
+
+    feat: float32 [B][H][W][4]; params: float32 [5377]; label: uint8 [B][H][W].
+    Returns (loss, logits[B][H][W], grad[5377] or None)."""
+    f = np.ascontiguousarray(feat, np.float32)
+    if f.ndim == 3:
+        f = f[None]
+    B, H, W, _ = f.shape
+    prm = np.ascontiguousarray(params, np.float32)
+    assert prm.size == NPARAM
+    logits = np.zeros((B, H, W), np.float32)
+    grad = np.zeros(NPARAM, np.float32) if want_grad else None
+    lb = None
+    if label is not None:
+        lb = np.ascontiguousarray(label, np.uint8).reshape(B, H, W)
+    loss = lib().oracle_lrnet(_p(f), _p(lb) if lb is not None else None, B, H, W, _p(prm),
+                              int(round_bf16), _p(grad) if grad is not None else None,
+                              _p(logits))
+    return loss, logits, grad
+
+
+def bf16(x: np.ndarray) -> np.ndarray:
+    x = np.asarray(x, np.float32)
+    f = lib().oracle_bf16
+    return np.array([f(float(v)) for v in x.reshape(-1)], np.float32).reshape(x.shape)
+
+
+def adam(w, m, v, g, lr, b1, b2, eps, step):
+    """One Adam step in place (FP32); b1^step and b2^step formed in FP32 by
+    repeated multiplication."""
+    b1t = np.float32(1.0)
+    b2t = np.float32(1.0)
+    for _ in range(step):
+        b1t = np.float32(b1t * np.float32(b1))
+        b2t = np.float32(b2t * np.float32(b2))
+    lib().oracle_adam(_p(w), _p(m), _p(v), _p(np.ascontiguousarray(g, np.float32)), w.size, lr,
+                      b1, b2, eps, float(b1t), float(b2t))
