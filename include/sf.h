@@ -1,0 +1,151 @@
+/*
+ * sf.h - C ABI of the MI355X (gfx950) stereo / scene-flow hot path.
+ *
+ * The method: two rectified, temporally adjacent stereo pairs on one image
+ * domain Omega (paper, Sec. 3); a disparity map D: Omega -> R+ per time step by
+ * semi-global matching over eight paths with a left-right consistency check
+ * that leaves it non-dense (Sec. 3.1, Eq. 1); a flow field F: Omega -> R^2
+ * (Sec. 3.2, supplied by the caller); and the combination into the scene-flow
+ * map S: Omega -> R^4, S(x) = (u, v, d0, d1) with d1 read bilinearly at
+ * x + F(x), undefined where x + F(x) leaves Omega or a disparity is invalid
+ * (Sec. 3.3, case definition and bilinear equation).
+ *
+ * Conventions shared by every entry point:
+ *   - All array arguments are DEVICE pointers to caller-owned memory unless a
+ *     comment says "host".  The library never allocates or frees them; where
+ *     scratch memory is needed the caller passes a workspace and its size.
+ *   - Images and maps are row-major [H][W]; cost and aggregated-cost volumes
+ *     are [H][W][D] with the disparity index fastest.
+ *   - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream)
+ *     and return without synchronising.
+ *   - Arguments are validated on the host before anything is launched.  On
+ *     failure nothing is enqueued and the status is returned; sf_last_error()
+ *     then holds a message for the calling thread.
+ *   - Direction numbering for path masks, r = (rx, ry), predecessor p - r:
+ *       0:(+1,0) 1:(-1,0) 2:(0,+1) 3:(0,-1) 4:(+1,+1) 5:(-1,+1) 6:(+1,-1) 7:(-1,-1)
+ */
+#ifndef SF_H
+#define SF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SF_OK 0
+#define SF_EINVAL 1        /* bad argument: NULL pointer, size <= 0, pitch < W, P2 < P1 ... */
+#define SF_EUNSUPPORTED 2  /* valid for the method, not supported by these kernels (e.g. D) */
+#define SF_EHIP 3          /* HIP runtime / launch error */
+#define SF_ENOMEM 4        /* workspace smaller than the required size */
+
+#define SF_ABI_VERSION 1
+#define SF_DMAX 256        /* largest disparity range the kernels accept */
+#define SF_CMAX 62         /* largest Hamming cost of the 9x7 census (62 bits) */
+
+int sf_abi_version(void);
+/* Message describing the last failure of an sf_* call on this thread ("" if none). */
+const char *sf_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Census transform (the matching cost of SGM, Sec. 3.1; the paper names none).
+ * 9 wide x 7 tall window; neighbours in row-major order with the centre
+ * skipped; bit = 1 iff neighbour < centre; the first neighbour lands in bit 61
+ * and the last in bit 0 (bits 63..62 are zero); pixels outside the image take
+ * the nearest edge pixel.
+ *   img    [H][pitch] uint8, pitch >= W
+ *   census [H][W] uint64 (output)
+ * Errors: SF_EINVAL for NULL pointers, H or W <= 0, pitch < W. */
+int sf_census(const uint8_t *img, int H, int W, int pitch, uint64_t *census, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Matching-cost volume: Hamming distance between the base pixel's census and
+ * the match pixel's, for every disparity d in [0, D).
+ *   base_is_right = 0: base = left view, match pixel (x - d, y)
+ *   base_is_right = 1: base = right view, match pixel (x + d, y)
+ * A match pixel outside the image costs SF_CMAX (62).
+ *   cen_base, cen_match [H][W] uint64;  cost [H][W][D] uint8 (output)
+ * Errors: SF_EINVAL (NULL, H/W <= 0, D < 1 or D > SF_DMAX). */
+int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, int D,
+            int base_is_right, uint8_t *cost, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Semi-global aggregation over the selected paths (Sec. 3.1: eight paths
+ * radiating from each pixel; recurrence of the cited SGM method).  For each
+ * direction r in path_mask, with predecessor p - r:
+ *   Lr(p, d) = C(p, d)                                   if p - r is outside
+ *   Lr(p, d) = C(p, d) + min(Lr(p-r, d), Lr(p-r, d-1) + P1, Lr(p-r, d+1) + P1,
+ *                            M + P2) - M,   M = min_k Lr(p-r, k)   otherwise
+ * (terms with d +- 1 outside [0, D) dropped) and S(p, d) = sum_r Lr(p, d).
+ * All values are exact integers: Lr <= 62 + P2 and S <= 8 (62 + P2).
+ *   cost      [H][W][D] uint8 (values <= 62)
+ *   S         [H][W][D] uint16 (output)
+ *   workspace device scratch of at least sf_sgm_workspace_bytes(H, W, D) bytes
+ * Supported: D a multiple of 32 in [32, 256]; 0 <= P1 <= P2 <= 8000;
+ * path_mask in [1, 255].
+ * Errors: SF_EINVAL (NULL, H/W <= 0, P2 < P1, P2 > 8000, mask 0 or > 255),
+ * SF_EUNSUPPORTED (D), SF_ENOMEM (ws_bytes too small). */
+size_t sf_sgm_workspace_bytes(int H, int W, int D);
+int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
+                     uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
+                     void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Winner-take-all, sub-pixel refinement, left-right check (Sec. 3.1: the
+ * check compares two computed disparity maps and removes inconsistent pixels,
+ * leaving a non-dense map) and, optionally, the learned stand-in's features.
+ *   d*      = smallest d with S(p, d) = min_k S(p, k)
+ *   d_sub   = d* + (S(d*-1) - S(d*+1)) / (2 (S(d*-1) - 2 S(d*) + S(d*+1)))
+ *             when 0 < d* < D-1 and the denominator is > 0, else d*
+ *             (one FP32 division, one FP32 addition)
+ *   valid   = q = x - d*_L >= 0 and |d*_L(x, y) - d*_R(q, y)| <= lr_tol
+ *   disp    = d_sub where valid, -1.0f elsewhere; the uint8 mask is authoritative
+ * Arguments:
+ *   S_left    [H][W][D] uint16, left-view aggregated costs
+ *   S_right   [H][W][D] uint16 right-view costs, or NULL: no check, valid := 1
+ *   wta_left  [H][W] int16 (output) d*_L, unmasked
+ *   wta_right [H][W] int16 (output) d*_R; required iff S_right != NULL
+ *   disp      [H][W] float (output);  valid [H][W] uint8 (output)
+ *   feat      [H][W][4] float (output) or NULL; needs img_left (pitch >= W):
+ *             k=0 I_L/255, k=1 d* / (D-1), k=2 S(d*)/(8 (62+P2)),
+ *             k=3 S2/max(S(d*),1) with S2 = min of S over |d - d*| >= 2
+ *             (S(d*) when no such d); FP32 divisions
+ * Supported D: any in [1, SF_DMAX].  Errors: SF_EINVAL. */
+int sf_wta_lr(const uint16_t *S_left, const uint16_t *S_right, const uint8_t *img_left, int pitch,
+              int H, int W, int D, int P2, int lr_tol, int16_t *wta_left, int16_t *wta_right,
+              float *disp, uint8_t *valid, float *feat, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Combination and triangulation (Sec. 3.3).
+ * For each pixel x = (x, y): (u, v) = flow, x' = x + u, y' = y + v.
+ * S(x) = (u, v, d0 = disp0(x), d1) is defined iff valid0(x), 0 <= x' <= W-1 and
+ * 0 <= y' <= H-1 (NaN fails), and the four taps (x0,y0) (x1,y0) (x0,y1) (x1,y1)
+ * with x0 = floor(x'), y0 = floor(y'), x1 = min(x0+1, W-1), y1 = min(y0+1, H-1)
+ * are valid in valid1.  d1 is the bilinear equation of Sec. 3.3 with
+ * fx = x' - x0, fy = y' - y0, its four terms ((D*w1)*w2) summed in the printed
+ * order, in FP32.
+ * With a camera (host pointer, NULL = no 3-D output): where S is defined and
+ * d0 > 0 and d1 > 0, Z = (f*B)/d, X = ((x - cx) Z)/f, Y = ((y - cy) Z)/f;
+ * xyz0 = P0 from (x, y, d0); motion = P1 - P0 with P1 from (x', y', d1).
+ *   disp0, disp1 [H][W] float; valid0, valid1 [H][W] uint8; flow [H][W][2] float
+ *   sf4 [H][W][4] float (output; 4x NaN where undefined)
+ *   valid [H][W] uint8 (output): bit 0 = S defined, bit 1 = 3-D defined
+ *   xyz0, motion [H][W][3] float (outputs, NaN where undefined); ignored if cam NULL
+ * Errors: SF_EINVAL. */
+typedef struct {
+    float f;   /* focal length, px */
+    float B;   /* baseline, m */
+    float cx;  /* principal point, px */
+    float cy;
+} sf_camera;
+
+int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
+               const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
+               float *sf4, uint8_t *valid, float *xyz0, float *motion, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SF_H */

@@ -1,0 +1,69 @@
+"""ctypes declarations of libsf.so (the C ABI in include/sf.h).
+
+The shared library is built in-tree by paper_1801_04720_amd/build.py.  There is
+no fallback of any kind: if the library is missing or fails to load, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsf.so")
+
+SF_OK, SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP, SF_ENOMEM = 0, 1, 2, 3, 4
+STATUS_NAMES = {0: "SF_OK", 1: "SF_EINVAL", 2: "SF_EUNSUPPORTED", 3: "SF_EHIP", 4: "SF_ENOMEM"}
+
+P = ct.c_void_p
+I = ct.c_int
+U32 = ct.c_uint32
+F = ct.c_float
+SZ = ct.c_size_t
+
+
+class SfCamera(ct.Structure):
+    _fields_ = [("f", ct.c_float), ("B", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float)]
+
+
+class SfError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "sf_abi_version": (I, []),
+    "sf_last_error": (ct.c_char_p, []),
+    "sf_census": (I, [P, I, I, I, P, P]),
+    "sf_cost": (I, [P, P, I, I, I, I, P, P]),
+    "sf_sgm_workspace_bytes": (SZ, [I, I, I]),
+    "sf_sgm_aggregate": (I, [P, I, I, I, I, I, U32, P, P, SZ, P]),
+    "sf_sgm_set_epilogue": (I, [I]),
+    "sf_wta_lr": (I, [P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
+    "sf_combine": (I, [P, P, P, P, P, I, I, ct.POINTER(SfCamera), P, P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib() -> ct.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is not built; run paper_1801_04720_amd/build.py (hipcc, gfx950)")
+        L = ct.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != SF_OK:
+        msg = lib().sf_last_error().decode(errors="replace")
+        raise SfError(status, msg)

@@ -1,0 +1,140 @@
+"""Python binding of the C ABI: the same entry points, torch tensors in/out.
+
+Argument marshalling only.  Every step of the path runs in the HIP kernels of
+libsf.so on the caller's current torch stream; torch provides device memory
+and streams.  Integer volumes use torch's signed dtypes as bit containers:
+census descriptors live in int64 tensors (view them as uint64), aggregated
+costs in int16 tensors (view them as uint16).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import torch
+
+from . import _lib
+from ._lib import SfCamera, check, lib
+
+CMAX = 62
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("sf: tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("sf: tensors must be contiguous")
+    return ct.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def abi_version() -> int:
+    return lib().sf_abi_version()
+
+
+def census(img: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """9x7 census of a uint8 [H][W] image -> int64 [H][W] (62-bit descriptors)."""
+    H, W = img.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int64, device=img.device)
+    check(lib().sf_census(_ptr(img), H, W, img.stride(0), _ptr(out), _stream(stream)))
+    return out
+
+
+def cost(cen_base, cen_match, D: int, base_is_right: bool, out=None, stream=None):
+    """Hamming cost volume uint8 [H][W][D]."""
+    H, W = cen_base.shape
+    if out is None:
+        out = torch.empty((H, W, D), dtype=torch.uint8, device=cen_base.device)
+    check(lib().sf_cost(_ptr(cen_base), _ptr(cen_match), H, W, D, int(base_is_right), _ptr(out),
+                        _stream(stream)))
+    return out
+
+
+def sgm_workspace_bytes(H: int, W: int, D: int) -> int:
+    return int(lib().sf_sgm_workspace_bytes(H, W, D))
+
+
+def sgm_set_epilogue(mode: int) -> None:
+    """0 = automatic, 1 = per-direction u8 slabs + sum, 2 = packed atomics into S."""
+    check(lib().sf_sgm_set_epilogue(mode))
+
+
+def sgm_aggregate(cost_vol, P1: int, P2: int, path_mask: int = 0xFF, out=None, workspace=None,
+                  stream=None):
+    """Aggregated costs S (int16 container of uint16 values) [H][W][D]."""
+    H, W, D = cost_vol.shape
+    if out is None:
+        out = torch.empty((H, W, D), dtype=torch.int16, device=cost_vol.device)
+    if workspace is None:
+        workspace = torch.empty(sgm_workspace_bytes(H, W, D), dtype=torch.uint8,
+                                device=cost_vol.device)
+    check(lib().sf_sgm_aggregate(_ptr(cost_vol), H, W, D, P1, P2, path_mask, _ptr(out),
+                                 _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def wta_lr(S_left, S_right=None, img_left=None, P2: int = 120, lr_tol: int = 1, want_feat=False,
+           out=None, stream=None):
+    """WTA + sub-pixel + LR check (+ features).
+
+    Returns dict with wta_left int16, wta_right int16 (or None), disp float32,
+    valid uint8, feat float32 [H][W][4] (or None)."""
+    H, W, D = S_left.shape
+    dev = S_left.device
+    o = out or {}
+    wl = o.get("wta_left")
+    if wl is None:
+        wl = torch.empty((H, W), dtype=torch.int16, device=dev)
+    wr = o.get("wta_right")
+    if S_right is not None and wr is None:
+        wr = torch.empty((H, W), dtype=torch.int16, device=dev)
+    disp = o.get("disp")
+    if disp is None:
+        disp = torch.empty((H, W), dtype=torch.float32, device=dev)
+    valid = o.get("valid")
+    if valid is None:
+        valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    feat = o.get("feat")
+    if want_feat and feat is None:
+        feat = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    if not want_feat:
+        feat = None
+    pitch = img_left.stride(0) if img_left is not None else W
+    check(lib().sf_wta_lr(_ptr(S_left), _ptr(S_right), _ptr(img_left), pitch, H, W, D, P2, lr_tol,
+                          _ptr(wl), _ptr(wr) if S_right is not None else None, _ptr(disp),
+                          _ptr(valid), _ptr(feat), _stream(stream)))
+    return {"wta_left": wl, "wta_right": wr if S_right is not None else None, "disp": disp,
+            "valid": valid, "feat": feat}
+
+
+def combine(disp0, valid0, disp1, valid1, flow, cam=None, out=None, stream=None):
+    """Scene-flow map (Sec. 3.3) and, with cam = (f, B, cx, cy), 3-D points / motion."""
+    H, W = disp0.shape
+    dev = disp0.device
+    o = out or {}
+    sf4 = o.get("sf4")
+    if sf4 is None:
+        sf4 = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    valid = o.get("valid")
+    if valid is None:
+        valid = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    xyz0 = motion = None
+    camp = None
+    if cam is not None:
+        xyz0 = o.get("xyz0")
+        if xyz0 is None:
+            xyz0 = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        motion = o.get("motion")
+        if motion is None:
+            motion = torch.empty((H, W, 3), dtype=torch.float32, device=dev)
+        camp = ct.byref(SfCamera(*[float(c) for c in cam]))
+    check(lib().sf_combine(_ptr(disp0), _ptr(valid0), _ptr(disp1), _ptr(valid1), _ptr(flow), H, W,
+                           camp, _ptr(sf4), _ptr(valid), _ptr(xyz0), _ptr(motion),
+                           _stream(stream)))
+    return {"sf4": sf4, "valid": valid, "xyz0": xyz0, "motion": motion}

@@ -1,0 +1,100 @@
+// Combination of the two disparity maps and the flow into the scene-flow map
+// (paper Sec. 3.3: the case definition of S, the bilinear interpolation
+// equation for D1 at x + F(x), and the 3-D reading of (u, v, d0, d1) through
+// the camera).  One thread per pixel; flow and outputs are read / written as
+// float2 / float4 / 3 x float, coalesced along rows.  Built without FMA
+// contraction so every product and sum is the FP32 operation stated.
+#include "sf_internal.hpp"
+
+namespace sf {
+
+__global__ __launch_bounds__(256) void combine_kernel(
+    const float *__restrict__ disp0, const uint8_t *__restrict__ valid0,
+    const float *__restrict__ disp1, const uint8_t *__restrict__ valid1,
+    const float2 *__restrict__ flow, int H, int W, int has_cam, sf_camera cam,
+    float4 *__restrict__ sf4, uint8_t *__restrict__ valid, float *__restrict__ xyz0,
+    float *__restrict__ motion)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= W) return;
+    const size_t i = (size_t)y * W + x;
+    const float2 uv = flow[i];
+    const float xp = (float)x + uv.x;
+    const float yp = (float)y + uv.y;
+    bool defined = false;
+    float d0 = 0.0f, d1 = 0.0f;
+    if (valid0[i] && xp >= 0.0f && xp <= (float)(W - 1) && yp >= 0.0f && yp <= (float)(H - 1)) {
+        const int x0 = (int)floorf(xp), y0 = (int)floorf(yp);
+        const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
+        const size_t i00 = (size_t)y0 * W + x0, i10 = (size_t)y0 * W + x1;
+        const size_t i01 = (size_t)y1 * W + x0, i11 = (size_t)y1 * W + x1;
+        if (valid1[i00] && valid1[i10] && valid1[i01] && valid1[i11]) {
+            const float fx = xp - (float)x0;
+            const float fy = yp - (float)y0;
+            const float t00 = (disp1[i00] * (1.0f - fx)) * (1.0f - fy);
+            const float t10 = (disp1[i10] * fx) * (1.0f - fy);
+            const float t01 = (disp1[i01] * (1.0f - fx)) * fy;
+            const float t11 = (disp1[i11] * fx) * fy;
+            d1 = ((t00 + t10) + t01) + t11;
+            d0 = disp0[i];
+            defined = true;
+        }
+    }
+    const float nanv = __builtin_nanf("");
+    uint8_t vb = 0;
+    if (defined) {
+        vb = 1;
+        sf4[i] = make_float4(uv.x, uv.y, d0, d1);
+    } else {
+        sf4[i] = make_float4(nanv, nanv, nanv, nanv);
+    }
+    if (has_cam) {
+        float o[6];
+        if (defined && d0 > 0.0f && d1 > 0.0f) {
+            vb |= 2;
+            const float fB = cam.f * cam.B;
+            const float Z0 = fB / d0;
+            const float X0 = (((float)x - cam.cx) * Z0) / cam.f;
+            const float Y0 = (((float)y - cam.cy) * Z0) / cam.f;
+            const float Z1 = fB / d1;
+            const float X1 = ((xp - cam.cx) * Z1) / cam.f;
+            const float Y1 = ((yp - cam.cy) * Z1) / cam.f;
+            o[0] = X0; o[1] = Y0; o[2] = Z0;
+            o[3] = X1 - X0; o[4] = Y1 - Y0; o[5] = Z1 - Z0;
+        } else {
+            for (int k = 0; k < 6; ++k) o[k] = nanv;
+        }
+        xyz0[3 * i + 0] = o[0];
+        xyz0[3 * i + 1] = o[1];
+        xyz0[3 * i + 2] = o[2];
+        motion[3 * i + 0] = o[3];
+        motion[3 * i + 1] = o[4];
+        motion[3 * i + 2] = o[5];
+    }
+    valid[i] = vb;
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
+                          const uint8_t *valid1, const float *flow, int H, int W,
+                          const sf_camera *cam, float *sf4, uint8_t *valid, float *xyz0,
+                          float *motion, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(disp0 && valid0 && disp1 && valid1 && flow && sf4 && valid, SF_EINVAL,
+               "sf_combine: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_combine: H and W must be positive");
+    SF_REQUIRE(H <= 65535, SF_EINVAL, "sf_combine: H > 65535");
+    SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL, "sf_combine: camera given without xyz0/motion");
+    sf_camera c = cam ? *cam : sf_camera{0.0f, 0.0f, 0.0f, 0.0f};
+    if (cam) SF_REQUIRE(c.f != 0.0f, SF_EINVAL, "sf_combine: focal length is zero");
+    dim3 grid((W + 255) / 256, H);
+    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, as_stream(stream), disp0, valid0, disp1,
+                       valid1, reinterpret_cast<const float2 *>(flow), H, W, cam ? 1 : 0, c,
+                       reinterpret_cast<float4 *>(sf4), valid, xyz0, motion);
+    return launch_status("combine_kernel");
+}

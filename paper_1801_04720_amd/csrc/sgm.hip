@@ -1,0 +1,383 @@
+// Semi-global path aggregation (paper Sec. 3.1: eight paths radiating from
+// each pixel; the per-path recurrence with penalties P1 / P2 of the cited SGM
+// method).
+//
+// Work decomposition (CDNA wave64):
+//   * one "path chain" = one scanline of one direction, walked from the image
+//     edge where its predecessor leaves the image;
+//   * a chain is owned by one 16-lane DPP row; lane j of the row holds the K =
+//     D/16 consecutive disparities [jK, jK+K) as K/2 packed u16 pairs, so the
+//     d-1 / d+1 neighbours come from v_alignbit inside a lane plus one
+//     row_shr / row_shl DPP move across lanes, and min_k Lr(p-r, k) is a
+//     4-step DPP butterfly inside the row (quad_perm, half-mirror, mirror);
+//   * a wave carries 4 chains, a 256-thread block 16; chains of all selected
+//     directions are scheduled in one launch, the long horizontal ones first.
+//   * Lr needs at most 62 + P2 <= 255 (u8) when P2 <= 193: each direction's
+//     Lr is then streamed to its own u8 slab and a second pass sums the slabs
+//     into S (u16).  Otherwise Lr is added into a zeroed S with packed 32-bit
+//     atomics (each u16 half stays below 8 (62 + P2) < 2^16, so no carry
+//     crosses halves).
+#include "sf_internal.hpp"
+
+namespace sf {
+
+constexpr int SGM_NT = 256;            // threads per block
+constexpr int SGM_G = 16;              // lanes per chain (one DPP row)
+constexpr int SGM_CPB = SGM_NT / SGM_G;  // chains per block
+constexpr uint32_t SGM_SENT = 0x7FFF7FFFu;  // "no neighbour" value, never the minimum
+
+__constant__ int c_dir[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
+                                {+1, +1}, {-1, +1}, {+1, -1}, {-1, -1}};
+
+struct PathTable {
+    int ndir;
+    int dir[8];
+    int slot[8];       // slab index of each selected direction
+    int off[9];        // chain-index prefix sums
+};
+
+__host__ __device__ inline int chains_of(int r, int H, int W)
+{
+    return r < 2 ? H : (r < 4 ? W : W + H - 1);
+}
+
+// Start pixel and length of chain l of direction r.
+__device__ __forceinline__ void chain_geometry(int r, int l, int H, int W, int &x, int &y, int &len)
+{
+    const int rx = c_dir[r][0], ry = c_dir[r][1];
+    if (ry == 0) {
+        x = rx > 0 ? 0 : W - 1;
+        y = l;
+        len = W;
+    } else if (rx == 0) {
+        x = l;
+        y = ry > 0 ? 0 : H - 1;
+        len = H;
+    } else {
+        const int xe = rx > 0 ? 0 : W - 1, ye = ry > 0 ? 0 : H - 1;
+        if (l < H) {
+            x = xe;
+            y = ry > 0 ? l : H - 1 - l;
+        } else {
+            const int k = l - H;  // 0 .. W-2, skipping the corner column
+            x = rx > 0 ? k + 1 : W - 2 - k;
+            y = ye;
+        }
+        const int nx = rx > 0 ? W - x : x + 1;
+        const int ny = ry > 0 ? H - y : y + 1;
+        len = min(nx, ny);
+    }
+}
+
+// Raw cost bytes of one lane for one pixel, and their unpacking into u16 pairs.
+template <int K>
+struct CostRaw {
+    static constexpr int N = (K % 4 == 0) ? K / 4 : K / 2;
+    uint32_t w[N];
+};
+
+template <int K>
+__device__ __forceinline__ void load_raw(const uint8_t *p, CostRaw<K> &r)
+{
+    if constexpr (K % 16 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 16; ++q) {
+            uint4 v = reinterpret_cast<const uint4 *>(p)[q];
+            r.w[4 * q + 0] = v.x;
+            r.w[4 * q + 1] = v.y;
+            r.w[4 * q + 2] = v.z;
+            r.w[4 * q + 3] = v.w;
+        }
+    } else if constexpr (K % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 8; ++q) {
+            uint2 v = reinterpret_cast<const uint2 *>(p)[q];
+            r.w[2 * q + 0] = v.x;
+            r.w[2 * q + 1] = v.y;
+        }
+    } else if constexpr (K % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) r.w[q] = reinterpret_cast<const uint32_t *>(p)[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) r.w[q] = reinterpret_cast<const uint16_t *>(p)[q];
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void unpack(const CostRaw<K> &r, uint32_t (&c)[K / 2])
+{
+    if constexpr (K % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) {
+            // bytes b0 b1 b2 b3 -> (b0, b1) and (b2, b3) as u16 pairs
+            c[2 * q + 0] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c010c00u);
+            c[2 * q + 1] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c030c02u);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q) c[q] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c010c00u);
+    }
+}
+
+template <int K, bool ATOMIC>
+struct Emit {
+    __device__ __forceinline__ static void run(const uint32_t (&L)[K / 2], uint8_t *slab_px,
+                                               uint16_t *s_px)
+    {
+        if constexpr (ATOMIC) {
+            uint32_t *s32 = reinterpret_cast<uint32_t *>(s_px);
+#pragma unroll
+            for (int i = 0; i < K / 2; ++i) atomicAdd(s32 + i, L[i]);
+        } else {
+            // Low byte of each u16 half -> K consecutive bytes.
+            if constexpr (K % 4 == 0) {
+                uint32_t b[K / 4];
+#pragma unroll
+                for (int q = 0; q < K / 4; ++q)
+                    b[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
+                if constexpr (K % 16 == 0) {
+#pragma unroll
+                    for (int q = 0; q < K / 16; ++q)
+                        reinterpret_cast<uint4 *>(slab_px)[q] =
+                            make_uint4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+                } else if constexpr (K % 8 == 0) {
+#pragma unroll
+                    for (int q = 0; q < K / 8; ++q)
+                        reinterpret_cast<uint2 *>(slab_px)[q] = make_uint2(b[2 * q], b[2 * q + 1]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < K / 4; ++q) reinterpret_cast<uint32_t *>(slab_px)[q] = b[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < K / 2; ++q)
+                    reinterpret_cast<uint16_t *>(slab_px)[q] =
+                        (uint16_t)__builtin_amdgcn_perm(0u, L[q], 0x0c0c0200u);
+            }
+        }
+    }
+};
+
+// Prefetch depth (steps) of the cost stream of one chain.
+constexpr int SGM_U = 8;
+
+template <int K, bool ATOMIC>
+__global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__restrict__ cost,
+                                                           int H, int W, int P1, int P2,
+                                                           PathTable tab, uint8_t *__restrict__ slab,
+                                                           uint16_t *__restrict__ S)
+{
+    constexpr int D = 16 * K;
+    constexpr int NP = K / 2;
+    const int g = blockIdx.x * SGM_CPB + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (g >= tab.off[tab.ndir]) return;
+    int k = 0;
+    while (g >= tab.off[k + 1]) ++k;
+    const int r = tab.dir[k];
+    const int l = g - tab.off[k];
+    int x, y, len;
+    chain_geometry(r, l, H, W, x, y, len);
+    const int rx = c_dir[r][0], ry = c_dir[r][1];
+    const size_t npx = (size_t)H * W;
+    const ptrdiff_t pstep = (ptrdiff_t)ry * W + rx;  // pixel-index step along the chain
+    size_t p = (size_t)y * W + x;
+    const uint8_t *cbase = cost + (size_t)j * K;
+    uint8_t *sbase = ATOMIC ? nullptr : slab + (size_t)tab.slot[k] * npx * D + (size_t)j * K;
+    uint16_t *Sbase = ATOMIC ? S + (size_t)j * K : nullptr;
+
+    const u16x2 vP1 = (u16x2)((unsigned short)P1);
+    uint32_t L[NP];
+    uint32_t M = 0;
+
+    // Cost of the steps [t0, t0 + U) of this chain.
+    auto fetch = [&](int t0, CostRaw<K>(&buf)[SGM_U]) {
+#pragma unroll
+        for (int u = 0; u < SGM_U; ++u) {
+            const int t = t0 + u;
+            if (t < len) load_raw<K>(cbase + (size_t)((ptrdiff_t)p + (ptrdiff_t)t * pstep) * D, buf[u]);
+        }
+    };
+    auto step = [&](int t, const CostRaw<K> &raw) {
+        if (t >= len) return;
+        uint32_t c[NP];
+        unpack<K>(raw, c);
+        const size_t pt = (size_t)((ptrdiff_t)p + (ptrdiff_t)t * pstep);
+        if (t == 0) {
+#pragma unroll
+            for (int i = 0; i < NP; ++i) L[i] = c[i];
+        } else {
+            const uint32_t below = dpp_fill<DPP_ROW_SHR1>(SGM_SENT, L[NP - 1]);
+            const uint32_t above = dpp_fill<DPP_ROW_SHL1>(SGM_SENT, L[0]);
+            const u16x2 vM = (u16x2)((unsigned short)M);
+            const u16x2 vMP2 = (u16x2)((unsigned short)(M + P2));
+            uint32_t nL[NP];
+#pragma unroll
+            for (int i = 0; i < NP; ++i) {
+                const uint32_t lo_nb = (i == 0) ? below : L[i - 1];
+                const uint32_t hi_nb = (i == NP - 1) ? above : L[i + 1];
+                const u16x2 minus = as_u16x2(__builtin_amdgcn_alignbit(L[i], lo_nb, 16));
+                const u16x2 plus = as_u16x2(__builtin_amdgcn_alignbit(hi_nb, L[i], 16));
+                u16x2 tt = __builtin_elementwise_min(minus, plus) + vP1;
+                tt = __builtin_elementwise_min(tt, as_u16x2(L[i]));
+                tt = __builtin_elementwise_min(tt, vMP2);
+                tt = tt - vM + as_u16x2(c[i]);
+                nL[i] = as_u32(tt);
+            }
+#pragma unroll
+            for (int i = 0; i < NP; ++i) L[i] = nL[i];
+        }
+        Emit<K, ATOMIC>::run(L, ATOMIC ? nullptr : sbase + pt * D, ATOMIC ? Sbase + pt * D : nullptr);
+        u16x2 m2 = as_u16x2(L[0]);
+#pragma unroll
+        for (int i = 1; i < NP; ++i) m2 = __builtin_elementwise_min(m2, as_u16x2(L[i]));
+        M = row16_min(min((uint32_t)m2.x, (uint32_t)m2.y));
+    };
+
+    CostRaw<K> bufA[SGM_U], bufB[SGM_U];
+    fetch(0, bufA);
+    for (int t0 = 0; t0 < len; t0 += 2 * SGM_U) {
+        fetch(t0 + SGM_U, bufB);
+#pragma unroll
+        for (int u = 0; u < SGM_U; ++u) step(t0 + u, bufA[u]);
+        fetch(t0 + 2 * SGM_U, bufA);
+#pragma unroll
+        for (int u = 0; u < SGM_U; ++u) step(t0 + SGM_U + u, bufB[u]);
+    }
+}
+
+// S[i] = sum over the n slabs of slab[k][i]; 16 cells per thread.
+__global__ __launch_bounds__(256) void slab_sum_kernel(const uint8_t *__restrict__ slab, int n,
+                                                       size_t ncell, uint16_t *__restrict__ S)
+{
+    const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (i >= ncell) return;
+    if (i + 16 <= ncell) {
+        uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // u16 pairs
+        for (int k = 0; k < n; ++k) {
+            uint4 v = *reinterpret_cast<const uint4 *>(slab + (size_t)k * ncell + i);
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc[2 * q] += __builtin_amdgcn_perm(0u, w[q], 0x0c010c00u);
+                acc[2 * q + 1] += __builtin_amdgcn_perm(0u, w[q], 0x0c030c02u);
+            }
+        }
+        uint4 *o = reinterpret_cast<uint4 *>(S + i);
+        o[0] = make_uint4(acc[0], acc[1], acc[2], acc[3]);
+        o[1] = make_uint4(acc[4], acc[5], acc[6], acc[7]);
+    } else {
+        for (size_t c = i; c < ncell; ++c) {
+            uint32_t s = 0;
+            for (int k = 0; k < n; ++k) s += slab[(size_t)k * ncell + c];
+            S[c] = (uint16_t)s;
+        }
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, size_t n, uint32_t v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t st = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st) p[i] = v;
+}
+
+// 0 = automatic, 1 = u8 slabs + sum, 2 = packed atomics into S.
+static int g_epilogue_mode = 0;
+
+template <int K>
+static void launch_paths(bool atomic, int nblk, hipStream_t st, const uint8_t *cost, int H, int W,
+                         int P1, int P2, const PathTable &tab, uint8_t *slab, uint16_t *S)
+{
+    if (atomic)
+        hipLaunchKernelGGL((sgm_paths_kernel<K, true>), dim3(nblk), dim3(SGM_NT), 0, st, cost, H,
+                           W, P1, P2, tab, slab, S);
+    else
+        hipLaunchKernelGGL((sgm_paths_kernel<K, false>), dim3(nblk), dim3(SGM_NT), 0, st, cost,
+                           H, W, P1, P2, tab, slab, S);
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_sgm_set_epilogue(int mode)
+{
+    if (mode < 0 || mode > 2) return fail(SF_EINVAL, "sf_sgm_set_epilogue: mode must be 0, 1 or 2");
+    g_epilogue_mode = mode;
+    return SF_OK;
+}
+
+extern "C" size_t sf_sgm_workspace_bytes(int H, int W, int D)
+{
+    if (H <= 0 || W <= 0 || D <= 0) return 0;
+    return (size_t)8 * H * W * D;
+}
+
+extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
+                                uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
+                                void *stream)
+{
+    clear_error();
+    SF_REQUIRE(cost && S, SF_EINVAL, "sf_sgm_aggregate: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_sgm_aggregate: H and W must be positive");
+    SF_REQUIRE(P1 >= 0 && P2 >= P1, SF_EINVAL, "sf_sgm_aggregate: need 0 <= P1 <= P2");
+    SF_REQUIRE(P2 <= 8000, SF_EINVAL, "sf_sgm_aggregate: P2 > 8000 would overflow uint16 S");
+    SF_REQUIRE(path_mask >= 1 && path_mask <= 255, SF_EINVAL,
+               "sf_sgm_aggregate: path_mask must be in [1, 255]");
+    SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_sgm_aggregate: D must be in [1, 256]");
+    SF_REQUIRE(D % 32 == 0, SF_EUNSUPPORTED,
+               "sf_sgm_aggregate: these kernels need D to be a multiple of 32");
+    PathTable tab{};
+    tab.off[0] = 0;
+    for (int r = 0; r < 8; ++r) {
+        if (!(path_mask & (1u << r))) continue;
+        tab.dir[tab.ndir] = r;
+        tab.slot[tab.ndir] = tab.ndir;
+        tab.off[tab.ndir + 1] = tab.off[tab.ndir] + chains_of(r, H, W);
+        ++tab.ndir;
+    }
+    const size_t ncell = (size_t)H * W * D;
+    bool atomic;
+    if (g_epilogue_mode == 2)
+        atomic = true;
+    else if (g_epilogue_mode == 1)
+        atomic = false;
+    else
+        atomic = false;
+    if (SF_CMAX + P2 > 255) atomic = true;  // Lr no longer fits a u8 slab
+    const size_t need = atomic ? 0 : (size_t)tab.ndir * ncell;
+    if (!atomic) {
+        SF_REQUIRE(workspace, SF_EINVAL, "sf_sgm_aggregate: NULL workspace");
+        SF_REQUIRE(ws_bytes >= need, SF_ENOMEM, "sf_sgm_aggregate: workspace too small");
+    }
+    hipStream_t st = as_stream(stream);
+    uint8_t *slab = static_cast<uint8_t *>(workspace);
+    if (atomic) {
+        size_t nw = ncell / 2;  // D is even
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(2048), dim3(256), 0, st,
+                           reinterpret_cast<uint32_t *>(S), nw, 0u);
+        int rc = launch_status("fill_u32_kernel");
+        if (rc) return rc;
+    }
+    const int nchains = tab.off[tab.ndir];
+    const int nblk = (nchains + SGM_CPB - 1) / SGM_CPB;
+    switch (D / 16) {
+    case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 6: launch_paths<6>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 8: launch_paths<8>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 10: launch_paths<10>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 12: launch_paths<12>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 14: launch_paths<14>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+    default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
+    }
+    int rc = launch_status("sgm_paths_kernel");
+    if (rc || atomic) return rc;
+    const size_t nthr = (ncell + 15) / 16;
+    hipLaunchKernelGGL(slab_sum_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st,
+                       slab, tab.ndir, ncell, S);
+    return launch_status("slab_sum_kernel");
+}

@@ -1,0 +1,136 @@
+// Winner-take-all with parabolic sub-pixel refinement, the left-right
+// consistency check (paper Sec. 3.1: two computed disparity maps are compared
+// and inconsistent pixels removed, leaving a non-dense map) and the per-pixel
+// features of the learned stand-in for that check.
+//
+// One 16-lane DPP row per pixel: lane j reads disparities [4c, 4c+4) for
+// c = j, j+16, ... (128 contiguous bytes per row per load), the (S, d) minimum
+// is a row butterfly on the key S * 512 + d, so ties go to the smallest d.
+#include "sf_internal.hpp"
+
+namespace sf {
+
+constexpr int WTA_NT = 256;
+constexpr int WTA_PPB = WTA_NT / 16;  // pixels per block
+
+struct WtaResult {
+    uint32_t key;  // S(d*) * 512 + d*
+};
+
+__device__ __forceinline__ uint32_t s_at(const uint16_t *s, int d) { return s[d]; }
+
+// Row-wide minimum key of one pixel's cost vector.
+__device__ __forceinline__ uint32_t wta_key(const uint16_t *__restrict__ s, int D, int j)
+{
+    uint32_t best = 0xFFFFFFFFu;
+    if ((D & 3) == 0) {
+        for (int c = j; c < (D >> 2); c += 16) {
+            uint2 v = reinterpret_cast<const uint2 *>(s)[c];
+            const int d = 4 * c;
+            best = min(best, ((v.x & 0xFFFFu) << 9) | (uint32_t)d);
+            best = min(best, ((v.x >> 16) << 9) | (uint32_t)(d + 1));
+            best = min(best, ((v.y & 0xFFFFu) << 9) | (uint32_t)(d + 2));
+            best = min(best, ((v.y >> 16) << 9) | (uint32_t)(d + 3));
+        }
+    } else {
+        for (int d = j; d < D; d += 16) best = min(best, ((uint32_t)s[d] << 9) | (uint32_t)d);
+    }
+    return row16_min(best);
+}
+
+// d* of the right view only.
+__global__ __launch_bounds__(WTA_NT) void wta_right_kernel(const uint16_t *__restrict__ S, int npx,
+                                                          int D, int16_t *__restrict__ wta)
+{
+    const int px = blockIdx.x * WTA_PPB + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (px >= npx) return;
+    const uint32_t key = wta_key(S + (size_t)px * D, D, j);
+    if (j == 0) wta[px] = (int16_t)(key & 511u);
+}
+
+__global__ __launch_bounds__(WTA_NT) void wta_left_kernel(
+    const uint16_t *__restrict__ S, const int16_t *__restrict__ wta_r, const uint8_t *__restrict__ img,
+    int pitch, int H, int W, int D, int P2, int tol, int16_t *__restrict__ wta,
+    float *__restrict__ disp, uint8_t *__restrict__ valid, float *__restrict__ feat)
+{
+    const int px = blockIdx.x * WTA_PPB + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (px >= H * W) return;
+    const uint16_t *s = S + (size_t)px * D;
+    const uint32_t key = wta_key(s, D, j);
+    const int ds = (int)(key & 511u);
+    const uint32_t smin = key >> 9;
+    uint32_t s2 = 0xFFFFFFFFu;
+    if (feat) {
+        // Second minimum over |d - d*| >= 2.
+        for (int d = j; d < D; d += 16) {
+            const int gap = d > ds ? d - ds : ds - d;
+            if (gap >= 2) s2 = min(s2, (uint32_t)s[d]);
+        }
+        s2 = row16_min(s2);
+    }
+    if (j != 0) return;
+    const int y = px / W, x = px - y * W;
+    float sub = (float)ds;
+    if (ds > 0 && ds < D - 1) {
+        const int a = s[ds - 1], b = (int)smin, c = s[ds + 1];
+        const int den = a - 2 * b + c;
+        if (den > 0) sub = (float)ds + (float)(a - c) / (float)(2 * den);
+    }
+    int ok = 1;
+    if (wta_r) {
+        const int q = x - ds;
+        ok = 0;
+        if (q >= 0) {
+            int diff = ds - (int)wta_r[(size_t)y * W + q];
+            diff = diff < 0 ? -diff : diff;
+            ok = diff <= tol;
+        }
+    }
+    wta[px] = (int16_t)ds;
+    disp[px] = ok ? sub : -1.0f;
+    valid[px] = (uint8_t)ok;
+    if (feat) {
+        if (s2 == 0xFFFFFFFFu) s2 = smin;
+        float4 f;
+        f.x = (float)img[(size_t)y * pitch + x] / 255.0f;
+        f.y = D > 1 ? (float)ds / (float)(D - 1) : 0.0f;
+        f.z = (float)smin / (float)(8 * (SF_CMAX + P2));
+        f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
+        reinterpret_cast<float4 *>(feat)[px] = f;
+    }
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_wta_lr(const uint16_t *S_left, const uint16_t *S_right, const uint8_t *img_left,
+                         int pitch, int H, int W, int D, int P2, int lr_tol, int16_t *wta_left,
+                         int16_t *wta_right, float *disp, uint8_t *valid, float *feat, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(S_left && wta_left && disp && valid, SF_EINVAL, "sf_wta_lr: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_wta_lr: H and W must be positive");
+    SF_REQUIRE((long long)H * W <= (1LL << 30), SF_EINVAL, "sf_wta_lr: image too large");
+    SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_wta_lr: D must be in [1, 256]");
+    SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_wta_lr: lr_tol < 0");
+    SF_REQUIRE(!S_right || wta_right, SF_EINVAL, "sf_wta_lr: S_right needs wta_right");
+    SF_REQUIRE(!feat || (img_left && pitch >= W), SF_EINVAL,
+               "sf_wta_lr: features need img_left with pitch >= W");
+    SF_REQUIRE(P2 >= 0 && P2 <= 8000, SF_EINVAL, "sf_wta_lr: P2 out of range");
+    hipStream_t st = as_stream(stream);
+    const int npx = H * W;
+    const int nblk = (npx + WTA_PPB - 1) / WTA_PPB;
+    if (S_right) {
+        hipLaunchKernelGGL(wta_right_kernel, dim3(nblk), dim3(WTA_NT), 0, st, S_right, npx, D,
+                           wta_right);
+        int rc = launch_status("wta_right_kernel");
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(wta_left_kernel, dim3(nblk), dim3(WTA_NT), 0, st, S_left,
+                       S_right ? wta_right : nullptr, img_left, pitch, H, W, D, P2, lr_tol,
+                       wta_left, disp, valid, feat);
+    return launch_status("wta_left_kernel");
+}

@@ -1,0 +1,52 @@
+"""Plain scene-flow frame on one GPU, composed from the C-ABI calls with all
+buffers allocated once (Sec. 3: SGM on the t0 and t1 pairs, Sec. 3.3: the
+combination with the given flow).
+
+Per frame: census of the four images; for each time step the left-base and
+right-base cost volumes and their 8-path aggregation, WTA + sub-pixel + LR
+check; then the combination and triangulation.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import api
+
+
+class PlainFrame:
+    def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
+                 cam=(721.5, 0.54, None, None), path_mask: int = 0xFF, device="cuda:0"):
+        self.H, self.W, self.D = H, W, D
+        self.P1, self.P2, self.tol, self.mask = P1, P2, lr_tol, path_mask
+        f, B, cx, cy = cam
+        self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
+        dev = torch.device(device)
+        e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
+        self.cen = [e(H, W, dt=torch.int64) for _ in range(4)]
+        self.cost = e(H, W, D, dt=torch.uint8)
+        self.S_left = e(H, W, D, dt=torch.int16)
+        self.S_right = e(H, W, D, dt=torch.int16)
+        self.ws = e(api.sgm_workspace_bytes(H, W, D), dt=torch.uint8)
+        self.maps = []
+        for _ in range(2):
+            self.maps.append({"wta_left": e(H, W, dt=torch.int16), "wta_right": e(H, W, dt=torch.int16),
+                              "disp": e(H, W, dt=torch.float32), "valid": e(H, W, dt=torch.uint8),
+                              "feat": None})
+        self.out = {"sf4": e(H, W, 4, dt=torch.float32), "valid": e(H, W, dt=torch.uint8),
+                    "xyz0": e(H, W, 3, dt=torch.float32), "motion": e(H, W, 3, dt=torch.float32)}
+
+    def disparity(self, t: int, left, right, cen_l, cen_r):
+        api.census(left, out=cen_l)
+        api.census(right, out=cen_r)
+        api.cost(cen_r, cen_l, self.D, True, out=self.cost)
+        api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_right, workspace=self.ws)
+        api.cost(cen_l, cen_r, self.D, False, out=self.cost)
+        api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_left, workspace=self.ws)
+        return api.wta_lr(self.S_left, self.S_right, None, self.P2, self.tol, out=self.maps[t])
+
+    def run(self, L0, R0, L1, R1, flow):
+        m0 = self.disparity(0, L0, R0, self.cen[0], self.cen[1])
+        m1 = self.disparity(1, L1, R1, self.cen[2], self.cen[3])
+        out = api.combine(m0["disp"], m0["valid"], m1["disp"], m1["valid"], flow, self.cam,
+                          out=self.out)
+        return m0, m1, out
