@@ -87,6 +87,11 @@ int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, i
  * Errors: SF_EINVAL (NULL, H/W <= 0, P2 < P1, P2 > 8000, mask 0 or > 255),
  * SF_EUNSUPPORTED (D), SF_ENOMEM (ws_bytes too small). */
 size_t sf_sgm_workspace_bytes(int H, int W, int D);
+/* Tuning knob for the aggregation's output stage: 0 = automatic (u8 slabs + sum
+ * while 62 + P2 <= 255, packed atomics otherwise), 1 = u8 slabs + sum,
+ * 2 = packed 32-bit atomics into a zero-filled S.  Results are identical.
+ * Process-wide; not thread-safe.  Errors: SF_EINVAL for other modes. */
+int sf_sgm_set_epilogue(int mode);
 int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
                      uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
                      void *stream);
@@ -143,6 +148,17 @@ typedef struct {
 int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
                const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
                float *sf4, uint8_t *valid, float *xyz0, float *motion, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timer for benchmarking.  While enabled, each timed launch (census,
+ * cost, sgm_paths, slab_sum, wta_right, wta_left, combine, ...) records a pair
+ * of HIP events on its own stream; sf_prof_query waits for and sums those of one
+ * kernel name.  At most max_launches launches are recorded per enable.  The
+ * events are created by sf_prof_enable (call it outside any timed region).
+ * Process-wide, single-threaded use.  Errors: SF_EINVAL, SF_EHIP. */
+int sf_prof_enable(int max_launches);
+int sf_prof_disable(void);
+int sf_prof_query(const char *kernel, double *total_ms, int *launches);
 
 #ifdef __cplusplus
 }

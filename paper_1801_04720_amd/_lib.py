@@ -43,6 +43,9 @@ SIGNATURES = {
     "sf_sgm_set_epilogue": (I, [I]),
     "sf_wta_lr": (I, [P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
     "sf_combine": (I, [P, P, P, P, P, I, I, ct.POINTER(SfCamera), P, P, P, P, P]),
+    "sf_prof_enable": (I, [I]),
+    "sf_prof_disable": (I, []),
+    "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),
 }
 
 _lib = None

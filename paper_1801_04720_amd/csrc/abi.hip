@@ -1,5 +1,8 @@
-// Status and error reporting of the C ABI.
+// Status and error reporting of the C ABI, and an opt-in per-kernel timer
+// (HIP events recorded on the launch stream around each timed launch).
 #include <cstring>
+#include <string>
+#include <vector>
 
 #include "sf_internal.hpp"
 
@@ -17,7 +20,75 @@ void set_error(const char *fmt, ...)
 
 void clear_error() { g_err[0] = 0; }
 
+// --- kernel timer ---------------------------------------------------------
+struct ProfRec {
+    std::string name;
+    hipEvent_t start, stop;
+};
+static bool g_prof_on = false;
+static std::vector<hipEvent_t> g_prof_pool;
+static size_t g_prof_next = 0;
+static std::vector<ProfRec> g_prof_recs;
+
+ProfScope::ProfScope(const char *name, hipStream_t st) : st_(st), idx_(-1)
+{
+    if (!g_prof_on || g_prof_next + 2 > g_prof_pool.size()) return;
+    ProfRec r{name, g_prof_pool[g_prof_next], g_prof_pool[g_prof_next + 1]};
+    g_prof_next += 2;
+    hipEventRecord(r.start, st);
+    idx_ = (int)g_prof_recs.size();
+    g_prof_recs.push_back(r);
+}
+
+ProfScope::~ProfScope()
+{
+    if (idx_ >= 0) hipEventRecord(g_prof_recs[idx_].stop, st_);
+}
+
 }  // namespace sf
+
+extern "C" int sf_prof_enable(int max_launches)
+{
+    using namespace sf;
+    clear_error();
+    SF_REQUIRE(max_launches > 0 && max_launches <= (1 << 20), SF_EINVAL,
+               "sf_prof_enable: max_launches out of range");
+    for (hipEvent_t e : g_prof_pool) hipEventDestroy(e);
+    g_prof_pool.assign((size_t)2 * max_launches, nullptr);
+    for (auto &e : g_prof_pool)
+        if (hipEventCreate(&e) != hipSuccess) return fail(SF_EHIP, "sf_prof_enable: hipEventCreate");
+    g_prof_next = 0;
+    g_prof_recs.clear();
+    g_prof_on = true;
+    return SF_OK;
+}
+
+extern "C" int sf_prof_disable(void)
+{
+    sf::g_prof_on = false;
+    return SF_OK;
+}
+
+extern "C" int sf_prof_query(const char *kernel, double *total_ms, int *launches)
+{
+    using namespace sf;
+    clear_error();
+    SF_REQUIRE(kernel && total_ms && launches, SF_EINVAL, "sf_prof_query: NULL pointer");
+    double tot = 0.0;
+    int n = 0;
+    for (const ProfRec &r : g_prof_recs) {
+        if (r.name != kernel) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return fail(SF_EHIP, "sf_prof_query: sync");
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            return fail(SF_EHIP, "sf_prof_query: elapsed");
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *launches = n;
+    return SF_OK;
+}
 
 extern "C" int sf_abi_version(void) { return SF_ABI_VERSION; }
 

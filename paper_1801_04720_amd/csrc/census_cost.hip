@@ -115,6 +115,7 @@ extern "C" int sf_census(const uint8_t *img, int H, int W, int pitch, uint64_t *
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_census: H and W must be positive");
     SF_REQUIRE(pitch >= W, SF_EINVAL, "sf_census: pitch < W");
     dim3 grid((W + CEN_TW - 1) / CEN_TW, (H + CEN_TH - 1) / CEN_TH);
+    ProfScope prof("census", as_stream(stream));
     hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TW, CEN_TH), 0, as_stream(stream), img, H,
                        W, pitch, census);
     return launch_status("census_kernel");
@@ -129,6 +130,7 @@ extern "C" int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int 
     SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_cost: D must be in [1, 256]");
     SF_REQUIRE(H <= 65535, SF_EINVAL, "sf_cost: H > 65535");
     dim3 grid((W + COST_TP - 1) / COST_TP, H);
+    ProfScope prof("cost", as_stream(stream));
     if (base_is_right)
         hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(COST_NT), 0, as_stream(stream), cen_base,
                            cen_match, H, W, D, cost);

@@ -93,6 +93,7 @@ extern "C" int sf_combine(const float *disp0, const uint8_t *valid0, const float
     sf_camera c = cam ? *cam : sf_camera{0.0f, 0.0f, 0.0f, 0.0f};
     if (cam) SF_REQUIRE(c.f != 0.0f, SF_EINVAL, "sf_combine: focal length is zero");
     dim3 grid((W + 255) / 256, H);
+    ProfScope prof("combine", as_stream(stream));
     hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, as_stream(stream), disp0, valid0, disp1,
                        valid1, reinterpret_cast<const float2 *>(flow), H, W, cam ? 1 : 0, c,
                        reinterpret_cast<float4 *>(sf4), valid, xyz0, motion);

@@ -24,6 +24,17 @@ inline int fail(int code, const char *what)
 
 inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Records HIP events around the enclosed launch when sf_prof_enable() is on.
+class ProfScope {
+  public:
+    ProfScope(const char *name, hipStream_t st);
+    ~ProfScope();
+
+  private:
+    hipStream_t st_;
+    int idx_;
+};
+
 // Check the launch that was just enqueued.
 inline int launch_status(const char *kernel)
 {

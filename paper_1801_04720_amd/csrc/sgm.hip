@@ -363,6 +363,8 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     }
     const int nchains = tab.off[tab.ndir];
     const int nblk = (nchains + SGM_CPB - 1) / SGM_CPB;
+    {
+    ProfScope prof("sgm_paths", st);
     switch (D / 16) {
     case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
     case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
@@ -374,9 +376,11 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
     default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
     }
+    }
     int rc = launch_status("sgm_paths_kernel");
     if (rc || atomic) return rc;
     const size_t nthr = (ncell + 15) / 16;
+    ProfScope prof("slab_sum", st);
     hipLaunchKernelGGL(slab_sum_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st,
                        slab, tab.ndir, ncell, S);
     return launch_status("slab_sum_kernel");

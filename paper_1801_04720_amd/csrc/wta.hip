@@ -124,11 +124,13 @@ extern "C" int sf_wta_lr(const uint16_t *S_left, const uint16_t *S_right, const 
     const int npx = H * W;
     const int nblk = (npx + WTA_PPB - 1) / WTA_PPB;
     if (S_right) {
+        ProfScope prof("wta_right", as_stream(stream));
         hipLaunchKernelGGL(wta_right_kernel, dim3(nblk), dim3(WTA_NT), 0, st, S_right, npx, D,
                            wta_right);
         int rc = launch_status("wta_right_kernel");
         if (rc) return rc;
     }
+    ProfScope prof("wta_left", as_stream(stream));
     hipLaunchKernelGGL(wta_left_kernel, dim3(nblk), dim3(WTA_NT), 0, st, S_left,
                        S_right ? wta_right : nullptr, img_left, pitch, H, W, D, P2, lr_tol,
                        wta_left, disp, valid, feat);
