@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--epilogue", type=int, default=0, help="0 auto, 1 u8 slabs, 2 atomics")
+    ap.add_argument("--pipeline", default="fused", choices=["fused", "persistent", "stages"],
+                    help="fused: sf_frame_run; persistent: same with persistent aggregation "
+                         "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -67,7 +70,7 @@ def main():
     import torch
 
     from paper_1801_04720_amd import _lib, api, synth
-    from paper_1801_04720_amd.pipeline import PlainFrame
+    from paper_1801_04720_amd.pipeline import FusedFrame, PlainFrame
 
     lib = _lib.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -77,7 +80,10 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     L0, R0, L1, R1, flow = t(fr.t0.left), t(fr.t0.right), t(fr.t1.left), t(fr.t1.right), t(fr.flow)
     api.sgm_set_epilogue(args.epilogue)
-    pipe = PlainFrame(H, W, D, device=dev)
+    if args.pipeline == "stages":
+        pipe = PlainFrame(H, W, D, device=dev)
+    else:
+        pipe = FusedFrame(H, W, D, persistent=args.pipeline == "persistent", device=dev)
     for _ in range(args.warmup):
         pipe.run(L0, R0, L1, R1, flow)
     torch.cuda.synchronize()
@@ -86,7 +92,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        m0, m1, out = pipe.run(L0, R0, L1, R1, flow)
+        res_run = pipe.run(L0, R0, L1, R1, flow)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     lib.sf_prof_disable()
@@ -96,19 +102,32 @@ def main():
     gcups_delivered = 2 * cells / (ms * 1e-3) / 1e9
     gcups_passes = 4 * cells / (ms * 1e-3) / 1e9
     breakdown = {}
-    for name in ["census", "cost", "sgm_paths", "slab_sum", "wta_right", "wta_left", "combine"]:
+    for name in ["census", "cost", "sgm_paths", "sgm_tasks", "slab_sum", "wta_right", "wta_left",
+                 "wta_slab_right", "wta_slab_left", "combine"]:
         tot, n = kernel_ms(lib, name)
         if n:
             breakdown[name] = {"avg_ms": tot / n, "launches": n, "ms_per_frame": tot / args.steps}
-    sg = breakdown["sgm_paths"]
+    # Dominant kernel: the path aggregation (one launch per view, or one for all 4 views).
+    if "sgm_tasks" in breakdown:
+        kname, views_per_launch = "sgm_tasks", 4
+    else:
+        kname, views_per_launch = "sgm_paths", 1
+    sg = breakdown[kname]
     avg_s = sg["avg_ms"] * 1e-3
-    achieved = 8 * cells / avg_s / 1e12  # u16 element ops: 8 per cell update
-    roofline = {"bound": "alu", "kernel": "sgm_paths", "achieved": achieved,
+    ops = 8 * cells * views_per_launch  # u16 element ops: 8 per cell update
+    achieved = ops / avg_s / 1e12
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": PEAK_U16_TOPS, "unit": "TOP/s (packed u16)",
                 "frac": achieved / PEAK_U16_TOPS, "traffic": None,
-                "avg_launch_ms": sg["avg_ms"], "gcups_per_pass": cells / avg_s / 1e9}
-    valid0 = float(m0["valid"].float().mean().item())
-    dens = float((out["valid"] & 1).float().mean().item())
+                "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"],
+                "gcups_per_launch": cells * views_per_launch / avg_s / 1e9}
+    if args.pipeline == "stages":
+        m0, m1, out = res_run
+        v0t, vt = m0["valid"], out["valid"]
+    else:
+        v0t, vt = res_run["valid0"], res_run["valid"]
+    valid0 = float(v0t.float().mean().item())
+    dens = float((vt & 1).float().mean().item())
     res = {
         "metric": METRIC,
         "value": gcups_delivered,
@@ -125,7 +144,7 @@ def main():
         "config": {"workload": "plain scene-flow frame 1242x375 D=128 (SGM t0+t1 incl. right "
                                "views and LR check, combination, triangulation)",
                    "H": H, "W": W, "D": D, "paths": 8, "P1": 10, "P2": 120, "lr_tol": 1,
-                   "epilogue": args.epilogue},
+                   "epilogue": args.epilogue, "pipeline": args.pipeline},
         "fps_plain": 1e3 / ms,
         "gcups_all_passes": gcups_passes,
         "lr_valid_frac_t0": valid0,

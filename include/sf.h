@@ -150,6 +150,39 @@ int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
                float *sf4, uint8_t *valid, float *xyz0, float *motion, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Plans.  A plan is a host object fixing sizes and parameters of a fused
+ * multi-stage run; it owns a small device buffer with its aggregation task
+ * table (allocated and written once by the create call, freed by destroy) and
+ * lays out the caller's workspace, whose size sf_plan_workspace_bytes reports.
+ * Runs allocate nothing and enqueue only kernel launches, so they can be
+ * captured in a HIP graph.  A plan may be run concurrently on different
+ * streams only with different workspaces. */
+typedef struct sf_plan_s *sf_plan;
+size_t sf_plan_workspace_bytes(sf_plan plan);
+int sf_plan_destroy(sf_plan plan);
+
+/* Plain scene-flow frame (Sec. 3 and Sec. 3.3 end to end): the stereo pairs at
+ * t0 and t1 go through census, left- and right-base costs, 8-path aggregation,
+ * WTA + sub-pixel + LR check (as sf_wta_lr, but summing the per-direction path
+ * costs on the fly instead of materialising S), then sf_combine's
+ * combination and triangulation with the given flow.
+ *   persistent: 0 = one block per aggregation task; 1 = persistent blocks
+ *               pulling tasks from a counter (same results).
+ * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535.
+ * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (device table upload). */
+int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int persistent,
+                         sf_plan *plan);
+/* L0, R0, L1, R1 [H][pitch] uint8; flow [H][W][2]; cam host pointer or NULL.
+ * Outputs: disp0/valid0 (t0 map), disp1/valid1 (t1 map), as sf_wta_lr;
+ * sf4/valid/xyz0/motion as sf_combine.  Errors: SF_EINVAL, SF_ENOMEM
+ * (workspace smaller than sf_plan_workspace_bytes), SF_EHIP. */
+int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8_t *L1,
+                 const uint8_t *R1, int pitch, const float *flow, const sf_camera *cam,
+                 float *disp0, uint8_t *valid0, float *disp1, uint8_t *valid1, float *sf4,
+                 uint8_t *valid, float *xyz0, float *motion, void *workspace, size_t ws_bytes,
+                 void *stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timer for benchmarking.  While enabled, each timed launch (census,
  * cost, sgm_paths, slab_sum, wta_right, wta_left, combine, ...) records a pair
  * of HIP events on its own stream; sf_prof_query waits for and sums those of one

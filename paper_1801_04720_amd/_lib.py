@@ -43,6 +43,11 @@ SIGNATURES = {
     "sf_sgm_set_epilogue": (I, [I]),
     "sf_wta_lr": (I, [P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
     "sf_combine": (I, [P, P, P, P, P, I, I, ct.POINTER(SfCamera), P, P, P, P, P]),
+    "sf_plan_workspace_bytes": (SZ, [P]),
+    "sf_plan_destroy": (I, [P]),
+    "sf_frame_plan_create": (I, [I, I, I, I, I, I, I, ct.POINTER(P)]),
+    "sf_frame_run": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P, P, SZ,
+                         P]),
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),

@@ -138,3 +138,42 @@ def combine(disp0, valid0, disp1, valid1, flow, cam=None, out=None, stream=None)
                            camp, _ptr(sf4), _ptr(valid), _ptr(xyz0), _ptr(motion),
                            _stream(stream)))
     return {"sf4": sf4, "valid": valid, "xyz0": xyz0, "motion": motion}
+
+
+class Plan:
+    """Owner of an sf_plan handle (destroyed with the object)."""
+
+    def __init__(self, handle: ct.c_void_p):
+        self.handle = handle
+
+    def workspace_bytes(self) -> int:
+        return int(lib().sf_plan_workspace_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().sf_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def frame_plan(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
+               persistent: bool = False) -> Plan:
+    h = ct.c_void_p()
+    check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, int(persistent), ct.byref(h)))
+    return Plan(h)
+
+
+def frame_run(plan: Plan, L0, R0, L1, R1, flow, cam, out: dict, workspace, stream=None):
+    """Fused plain frame; `out` holds disp0, valid0, disp1, valid1, sf4, valid, xyz0, motion."""
+    camp = ct.byref(SfCamera(*[float(c) for c in cam])) if cam is not None else None
+    check(lib().sf_frame_run(plan.handle, _ptr(L0), _ptr(R0), _ptr(L1), _ptr(R1), L0.stride(0),
+                             _ptr(flow), camp, _ptr(out["disp0"]), _ptr(out["valid0"]),
+                             _ptr(out["disp1"]), _ptr(out["valid1"]), _ptr(out["sf4"]),
+                             _ptr(out["valid"]), _ptr(out.get("xyz0")), _ptr(out.get("motion")),
+                             _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out

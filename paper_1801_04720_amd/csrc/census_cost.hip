@@ -2,6 +2,7 @@
 // SGM, paper Sec. 3.1; the 9x7 census and Hamming distance are the workload's
 // choice, the paper names no cost).
 #include "sf_internal.hpp"
+#include "stages.hpp"
 
 namespace sf {
 
@@ -12,10 +13,11 @@ constexpr int CEN_RY = 3;   // window half-height (7 tall)
 
 // One thread per pixel; the (TH + 6) x (TW + 8) window of the tile is staged
 // in LDS with clamp-to-edge, coalesced along rows.
-__global__ __launch_bounds__(CEN_TW *CEN_TH) void census_kernel(const uint8_t *__restrict__ img,
-                                                                 int H, int W, int pitch,
-                                                                 uint64_t *__restrict__ out)
+__global__ __launch_bounds__(CEN_TW *CEN_TH) void census_kernel(CensusArgs a)
 {
+    const int H = a.H, W = a.W, pitch = a.pitch;
+    const uint8_t *__restrict__ img = a.img[blockIdx.z];
+    uint64_t *__restrict__ out = a.out[blockIdx.z];
     constexpr int LW = CEN_TW + 2 * CEN_RX;
     constexpr int LH = CEN_TH + 2 * CEN_RY;
     __shared__ uint8_t tile[LH][LW];
@@ -57,11 +59,13 @@ constexpr int COST_NT = 256;  // threads per block
 // cost[(y W + x) D + d] = popcount(base(x) ^ match(x -/+ d)), or 62 outside.
 // The block's base and match census segments are staged in LDS; the block's
 // output (COST_TP * D contiguous bytes) is written in coalesced 32-bit words.
-template <bool RIGHT>
-__global__ __launch_bounds__(COST_NT) void cost_kernel(const uint64_t *__restrict__ cb,
-                                                       const uint64_t *__restrict__ cm, int H,
-                                                       int W, int D, uint8_t *__restrict__ cost)
+__global__ __launch_bounds__(COST_NT) void cost_kernel(CostArgs a)
 {
+    const int H = a.H, W = a.W, D = a.D;
+    const uint64_t *__restrict__ cb = a.base[blockIdx.z];
+    const uint64_t *__restrict__ cm = a.match[blockIdx.z];
+    uint8_t *__restrict__ cost = a.cost[blockIdx.z];
+    const bool RIGHT = a.right[blockIdx.z] != 0;
     __shared__ uint64_t sb[COST_TP];
     __shared__ uint64_t sm[COST_TP + SF_DMAX];
     const int y = blockIdx.y;
@@ -103,6 +107,22 @@ __global__ __launch_bounds__(COST_NT) void cost_kernel(const uint64_t *__restric
     }
 }
 
+int launch_census(const CensusArgs &a, hipStream_t st)
+{
+    dim3 grid((a.W + CEN_TW - 1) / CEN_TW, (a.H + CEN_TH - 1) / CEN_TH, a.n);
+    ProfScope prof("census", st);
+    hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TW, CEN_TH), 0, st, a);
+    return launch_status("census_kernel");
+}
+
+int launch_cost(const CostArgs &a, hipStream_t st)
+{
+    dim3 grid((a.W + COST_TP - 1) / COST_TP, a.H, a.n);
+    ProfScope prof("cost", st);
+    hipLaunchKernelGGL(cost_kernel, grid, dim3(COST_NT), 0, st, a);
+    return launch_status("cost_kernel");
+}
+
 }  // namespace sf
 
 using namespace sf;
@@ -114,11 +134,15 @@ extern "C" int sf_census(const uint8_t *img, int H, int W, int pitch, uint64_t *
     SF_REQUIRE(img && census, SF_EINVAL, "sf_census: NULL pointer");
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_census: H and W must be positive");
     SF_REQUIRE(pitch >= W, SF_EINVAL, "sf_census: pitch < W");
-    dim3 grid((W + CEN_TW - 1) / CEN_TW, (H + CEN_TH - 1) / CEN_TH);
-    ProfScope prof("census", as_stream(stream));
-    hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TW, CEN_TH), 0, as_stream(stream), img, H,
-                       W, pitch, census);
-    return launch_status("census_kernel");
+    SF_REQUIRE(H <= 65535 * CEN_TH, SF_EINVAL, "sf_census: H too large");
+    CensusArgs a{};
+    a.img[0] = img;
+    a.out[0] = census;
+    a.n = 1;
+    a.H = H;
+    a.W = W;
+    a.pitch = pitch;
+    return launch_census(a, as_stream(stream));
 }
 
 extern "C" int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, int D,
@@ -129,13 +153,14 @@ extern "C" int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int 
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_cost: H and W must be positive");
     SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_cost: D must be in [1, 256]");
     SF_REQUIRE(H <= 65535, SF_EINVAL, "sf_cost: H > 65535");
-    dim3 grid((W + COST_TP - 1) / COST_TP, H);
-    ProfScope prof("cost", as_stream(stream));
-    if (base_is_right)
-        hipLaunchKernelGGL(cost_kernel<true>, grid, dim3(COST_NT), 0, as_stream(stream), cen_base,
-                           cen_match, H, W, D, cost);
-    else
-        hipLaunchKernelGGL(cost_kernel<false>, grid, dim3(COST_NT), 0, as_stream(stream),
-                           cen_base, cen_match, H, W, D, cost);
-    return launch_status("cost_kernel");
+    CostArgs a{};
+    a.base[0] = cen_base;
+    a.match[0] = cen_match;
+    a.cost[0] = cost;
+    a.right[0] = base_is_right ? 1 : 0;
+    a.n = 1;
+    a.H = H;
+    a.W = W;
+    a.D = D;
+    return launch_cost(a, as_stream(stream));
 }

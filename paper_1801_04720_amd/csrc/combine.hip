@@ -5,6 +5,7 @@
 // float2 / float4 / 3 x float, coalesced along rows.  Built without FMA
 // contraction so every product and sum is the FP32 operation stated.
 #include "sf_internal.hpp"
+#include "stages.hpp"
 
 namespace sf {
 
@@ -75,6 +76,19 @@ __global__ __launch_bounds__(256) void combine_kernel(
     valid[i] = vb;
 }
 
+int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
+                   const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
+                   float *sf4, uint8_t *valid, float *xyz0, float *motion, hipStream_t st)
+{
+    sf_camera c = cam ? *cam : sf_camera{0.0f, 0.0f, 0.0f, 0.0f};
+    dim3 grid((W + 255) / 256, H);
+    ProfScope prof("combine", st);
+    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, st, disp0, valid0, disp1, valid1,
+                       reinterpret_cast<const float2 *>(flow), H, W, cam ? 1 : 0, c,
+                       reinterpret_cast<float4 *>(sf4), valid, xyz0, motion);
+    return launch_status("combine_kernel");
+}
+
 }  // namespace sf
 
 using namespace sf;
@@ -90,12 +104,7 @@ extern "C" int sf_combine(const float *disp0, const uint8_t *valid0, const float
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_combine: H and W must be positive");
     SF_REQUIRE(H <= 65535, SF_EINVAL, "sf_combine: H > 65535");
     SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL, "sf_combine: camera given without xyz0/motion");
-    sf_camera c = cam ? *cam : sf_camera{0.0f, 0.0f, 0.0f, 0.0f};
-    if (cam) SF_REQUIRE(c.f != 0.0f, SF_EINVAL, "sf_combine: focal length is zero");
-    dim3 grid((W + 255) / 256, H);
-    ProfScope prof("combine", as_stream(stream));
-    hipLaunchKernelGGL(combine_kernel, grid, dim3(256), 0, as_stream(stream), disp0, valid0, disp1,
-                       valid1, reinterpret_cast<const float2 *>(flow), H, W, cam ? 1 : 0, c,
-                       reinterpret_cast<float4 *>(sf4), valid, xyz0, motion);
-    return launch_status("combine_kernel");
+    if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_combine: focal length is zero");
+    return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion,
+                          as_stream(stream));
 }

@@ -1,0 +1,202 @@
+// Fused plain scene-flow frame (paper Sec. 3: SGM on the stereo pairs at t0
+// and t1 with the left-right check, Sec. 3.3: combination with the flow).
+//
+// A frame plan fixes the size and parameters, lays out the caller's workspace
+// and holds the aggregation task table of the four views (L0, R0, L1, R1 as
+// bases) in a small device buffer written once at plan creation.  A run
+// enqueues six launches: census of the 4 images, 4 cost volumes, one
+// aggregation over all 4 views (u8 slabs), WTA of both right views, WTA +
+// sub-pixel + LR check of both left views (slabs summed on the fly, S never
+// written), and the combination.
+#include <cstring>
+#include <new>
+
+#include "sf_internal.hpp"
+#include "sgm_tasks.hpp"
+#include "stages.hpp"
+#include "plan.hpp"
+
+namespace sf {
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::vector<AggTask> &tasks)
+{
+    p.ntasks = (int)tasks.size();
+    p.nviews = (int)views.size();
+    const size_t bv = views.size() * sizeof(AggView), bt = tasks.size() * sizeof(AggTask);
+    if (hipMalloc(&p.d_tables, align256(bv) + bt + 256) != hipSuccess)
+        return fail(SF_EHIP, "plan: hipMalloc of the task table failed");
+    p.d_views = reinterpret_cast<AggView *>(p.d_tables);
+    p.d_tasks = reinterpret_cast<AggTask *>(static_cast<uint8_t *>(p.d_tables) + align256(bv));
+    p.d_counter = reinterpret_cast<int *>(static_cast<uint8_t *>(p.d_tables) + align256(bv) + bt);
+    if (hipMemcpy(p.d_views, views.data(), bv, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p.d_tasks, tasks.data(), bt, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(SF_EHIP, "plan: upload of the task table failed");
+    return SF_OK;
+}
+
+int default_persistent_blocks()
+{
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return ncu * 8;  // 8 blocks of 4 waves per CU
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int persistent,
+                                    sf_plan *out)
+{
+    clear_error();
+    SF_REQUIRE(out, SF_EINVAL, "sf_frame_plan_create: NULL out");
+    *out = nullptr;
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_frame_plan_create: H and W must be positive");
+    SF_REQUIRE(H <= 65535 && (long long)H * W <= (1LL << 28), SF_EINVAL,
+               "sf_frame_plan_create: image too large");
+    SF_REQUIRE(P1 >= 0 && P2 >= P1, SF_EINVAL, "sf_frame_plan_create: need 0 <= P1 <= P2");
+    SF_REQUIRE(SF_CMAX + P2 <= 255, SF_EUNSUPPORTED,
+               "sf_frame_plan_create: the fused frame needs 62 + P2 <= 255 (u8 path costs)");
+    SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_frame_plan_create: lr_tol < 0");
+    SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED,
+               "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
+    Plan *p = new (std::nothrow) Plan();
+    if (!p) return fail(SF_ENOMEM, "sf_frame_plan_create: out of host memory");
+    p->kind = Plan::FRAME;
+    p->H = H;
+    p->W = W;
+    p->D = D;
+    p->P1 = P1;
+    p->P2 = P2;
+    p->tol = lr_tol;
+    const size_t npx = (size_t)H * W, ncell = npx * D;
+    size_t off = 0;
+    for (int i = 0; i < 4; ++i) { p->off_cen[i] = off; off += align256(npx * 8); }
+    for (int i = 0; i < 4; ++i) { p->off_cost[i] = off; off += align256(ncell); }
+    for (int i = 0; i < 4; ++i) { p->off_slab[i] = off; off += align256(8 * ncell); }
+    for (int i = 0; i < 2; ++i) { p->off_wtar[i] = off; off += align256(npx * 2); }
+    for (int i = 0; i < 2; ++i) { p->off_wtal[i] = off; off += align256(npx * 2); }
+    p->ws_bytes = off;
+    std::vector<AggView> views(4);
+    std::vector<AggTask> tasks;
+    std::vector<int> lens;
+    for (int i = 0; i < 4; ++i) {
+        AggView &v = views[i];
+        v.cost_off = p->off_cost[i];
+        v.slab_off = p->off_slab[i];
+        v.H = H;
+        v.W = W;
+        v.K = D / 16;
+        v.P1 = P1;
+        v.P2 = P2;
+        v.ndir = 8;
+        for (int r = 0; r < 8; ++r) v.dir[r] = r;
+        append_agg_tasks(tasks, lens, i, v);
+    }
+    sort_tasks_longest_first(tasks, lens);
+    int rc = plan_upload_tables(*p, views, tasks);
+    if (rc) {
+        sf_plan_destroy(reinterpret_cast<sf_plan>(p));
+        return rc;
+    }
+    p->persistent_blocks = persistent ? default_persistent_blocks() : 0;
+    *out = reinterpret_cast<sf_plan>(p);
+    return SF_OK;
+}
+
+extern "C" size_t sf_plan_workspace_bytes(sf_plan plan)
+{
+    return plan ? reinterpret_cast<Plan *>(plan)->ws_bytes : 0;
+}
+
+extern "C" int sf_plan_destroy(sf_plan plan)
+{
+    if (!plan) return SF_OK;
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    if (p->d_tables) hipFree(p->d_tables);
+    delete p;
+    return SF_OK;
+}
+
+extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8_t *L1,
+                            const uint8_t *R1, int pitch, const float *flow, const sf_camera *cam,
+                            float *disp0, uint8_t *valid0, float *disp1, uint8_t *valid1,
+                            float *sf4, uint8_t *valid, float *xyz0, float *motion,
+                            void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(plan, SF_EINVAL, "sf_frame_run: NULL plan");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    SF_REQUIRE(p->kind == Plan::FRAME, SF_EINVAL, "sf_frame_run: not a frame plan");
+    SF_REQUIRE(L0 && R0 && L1 && R1 && flow && disp0 && valid0 && disp1 && valid1 && sf4 && valid,
+               SF_EINVAL, "sf_frame_run: NULL pointer");
+    SF_REQUIRE(pitch >= p->W, SF_EINVAL, "sf_frame_run: pitch < W");
+    SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL, "sf_frame_run: camera given without xyz0/motion");
+    if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_frame_run: focal length is zero");
+    SF_REQUIRE(workspace, SF_EINVAL, "sf_frame_run: NULL workspace");
+    SF_REQUIRE(ws_bytes >= p->ws_bytes, SF_ENOMEM, "sf_frame_run: workspace too small");
+    hipStream_t st = as_stream(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    const int H = p->H, W = p->W, D = p->D;
+    auto at = [&](size_t off) { return ws + off; };
+    const uint8_t *img[4] = {L0, R0, L1, R1};
+    uint64_t *cen[4];
+    for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
+
+    CensusArgs ca{};
+    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; }
+    ca.n = 4; ca.H = H; ca.W = W; ca.pitch = pitch;
+    int rc = launch_census(ca, st);
+    if (rc) return rc;
+
+    // Views: 0 = L0 base, 1 = R0 base, 2 = L1 base, 3 = R1 base.
+    CostArgs co{};
+    for (int t = 0; t < 2; ++t) {
+        co.base[2 * t] = cen[2 * t];      co.match[2 * t] = cen[2 * t + 1];  co.right[2 * t] = 0;
+        co.base[2 * t + 1] = cen[2 * t + 1]; co.match[2 * t + 1] = cen[2 * t]; co.right[2 * t + 1] = 1;
+    }
+    for (int i = 0; i < 4; ++i) co.cost[i] = at(p->off_cost[i]);
+    co.n = 4; co.H = H; co.W = W; co.D = D;
+    rc = launch_cost(co, st);
+    if (rc) return rc;
+
+    rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, ws, p->d_counter, p->persistent_blocks, st);
+    if (rc) return rc;
+
+    int16_t *wtar[2], *wtal[2];
+    for (int t = 0; t < 2; ++t) {
+        wtar[t] = reinterpret_cast<int16_t *>(at(p->off_wtar[t]));
+        wtal[t] = reinterpret_cast<int16_t *>(at(p->off_wtal[t]));
+    }
+    WtaArgs wr{};
+    for (int t = 0; t < 2; ++t) {
+        WtaView &v = wr.v[t];
+        v.slab = at(p->off_slab[2 * t + 1]);
+        v.wta = wtar[t];
+        v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 1;
+    }
+    wr.n = 2;
+    rc = launch_wta_slabs(wr, st);
+    if (rc) return rc;
+
+    WtaArgs wl{};
+    float *dsp[2] = {disp0, disp1};
+    uint8_t *vld[2] = {valid0, valid1};
+    for (int t = 0; t < 2; ++t) {
+        WtaView &v = wl.v[t];
+        v.slab = at(p->off_slab[2 * t]);
+        v.wta_r = wtar[t];
+        v.wta = wtal[t];
+        v.disp = dsp[t];
+        v.valid = vld[t];
+        v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 0;
+    }
+    wl.n = 2;
+    rc = launch_wta_slabs(wl, st);
+    if (rc) return rc;
+
+    return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
+}

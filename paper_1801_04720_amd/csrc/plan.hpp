@@ -1,0 +1,31 @@
+// Host-side plan objects behind the opaque sf_plan handle.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "sf.h"
+#include "sgm_tasks.hpp"
+
+namespace sf {
+
+struct Plan {
+    enum Kind { FRAME, BATCH, LRNET } kind = FRAME;
+    int H = 0, W = 0, D = 0, P1 = 0, P2 = 0, tol = 0;
+    size_t ws_bytes = 0;
+    // Frame workspace layout (byte offsets).
+    size_t off_cen[4] = {}, off_cost[4] = {}, off_slab[4] = {}, off_wtar[2] = {}, off_wtal[2] = {};
+    // Aggregation task table (plan-owned device memory).
+    void *d_tables = nullptr;
+    AggView *d_views = nullptr;
+    AggTask *d_tasks = nullptr;
+    int *d_counter = nullptr;
+    int ntasks = 0, nviews = 0;
+    int persistent_blocks = 0;
+};
+
+int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::vector<AggTask> &tasks);
+int default_persistent_blocks();
+
+}  // namespace sf

@@ -10,20 +10,26 @@
 //     d-1 / d+1 neighbours come from v_alignbit inside a lane plus one
 //     row_shr / row_shl DPP move across lanes, and min_k Lr(p-r, k) is a
 //     4-step DPP butterfly inside the row (quad_perm, half-mirror, mirror);
-//   * a wave carries 4 chains, a 256-thread block 16; chains of all selected
-//     directions are scheduled in one launch, the long horizontal ones first.
+//   * a wave carries 4 chains, a 256-thread block 16.
 //   * Lr needs at most 62 + P2 <= 255 (u8) when P2 <= 193: each direction's
-//     Lr is then streamed to its own u8 slab and a second pass sums the slabs
-//     into S (u16).  Otherwise Lr is added into a zeroed S with packed 32-bit
-//     atomics (each u16 half stays below 8 (62 + P2) < 2^16, so no carry
-//     crosses halves).
+//     Lr is then streamed to its own u8 slab and the consumer sums the slabs
+//     (a separate pass into S, or on the fly inside WTA).  Otherwise Lr is added
+//     into a zeroed S with packed 32-bit atomics (each u16 half stays below
+//     8 (62 + P2) < 2^16, so no carry crosses halves).
+//
+// Two launch shapes share the chain code:
+//   * sgm_paths_kernel: one view, the block index enumerates its chains;
+//   * sgm_tasks_kernel: many views (the four of a scene-flow frame, or a batch
+//     of uneven stereo pairs) from a task table sorted longest chains first,
+//     each block one task of up to 16 chains of one view and direction, K
+//     chosen per task; optionally persistent, pulling tasks from a counter.
 #include "sf_internal.hpp"
+#include "sgm_tasks.hpp"
 
 namespace sf {
 
-constexpr int SGM_NT = 256;            // threads per block
-constexpr int SGM_G = 16;              // lanes per chain (one DPP row)
-constexpr int SGM_CPB = SGM_NT / SGM_G;  // chains per block
+constexpr int SGM_NT = 256;              // threads per block
+constexpr int SGM_CPB = SGM_NT / 16;     // chains per block
 constexpr uint32_t SGM_SENT = 0x7FFF7FFFu;  // "no neighbour" value, never the minimum
 
 __constant__ int c_dir[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
@@ -32,14 +38,8 @@ __constant__ int c_dir[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
 struct PathTable {
     int ndir;
     int dir[8];
-    int slot[8];       // slab index of each selected direction
     int off[9];        // chain-index prefix sums
 };
-
-__host__ __device__ inline int chains_of(int r, int H, int W)
-{
-    return r < 2 ? H : (r < 4 ? W : W + H - 1);
-}
 
 // Start pixel and length of chain l of direction r.
 __device__ __forceinline__ void chain_geometry(int r, int l, int H, int W, int &x, int &y, int &len)
@@ -121,70 +121,61 @@ __device__ __forceinline__ void unpack(const CostRaw<K> &r, uint32_t (&c)[K / 2]
 }
 
 template <int K, bool ATOMIC>
-struct Emit {
-    __device__ __forceinline__ static void run(const uint32_t (&L)[K / 2], uint8_t *slab_px,
-                                               uint16_t *s_px)
-    {
-        if constexpr (ATOMIC) {
-            uint32_t *s32 = reinterpret_cast<uint32_t *>(s_px);
+__device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_px, uint16_t *s_px)
+{
+    if constexpr (ATOMIC) {
+        uint32_t *s32 = reinterpret_cast<uint32_t *>(s_px);
 #pragma unroll
-            for (int i = 0; i < K / 2; ++i) atomicAdd(s32 + i, L[i]);
-        } else {
-            // Low byte of each u16 half -> K consecutive bytes.
-            if constexpr (K % 4 == 0) {
-                uint32_t b[K / 4];
+        for (int i = 0; i < K / 2; ++i) atomicAdd(s32 + i, L[i]);
+    } else {
+        // Low byte of each u16 half -> K consecutive bytes.
+        if constexpr (K % 4 == 0) {
+            uint32_t b[K / 4];
 #pragma unroll
-                for (int q = 0; q < K / 4; ++q)
-                    b[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
-                if constexpr (K % 16 == 0) {
+            for (int q = 0; q < K / 4; ++q)
+                b[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
+            if constexpr (K % 16 == 0) {
 #pragma unroll
-                    for (int q = 0; q < K / 16; ++q)
-                        reinterpret_cast<uint4 *>(slab_px)[q] =
-                            make_uint4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
-                } else if constexpr (K % 8 == 0) {
+                for (int q = 0; q < K / 16; ++q)
+                    reinterpret_cast<uint4 *>(slab_px)[q] =
+                        make_uint4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+            } else if constexpr (K % 8 == 0) {
 #pragma unroll
-                    for (int q = 0; q < K / 8; ++q)
-                        reinterpret_cast<uint2 *>(slab_px)[q] = make_uint2(b[2 * q], b[2 * q + 1]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < K / 4; ++q) reinterpret_cast<uint32_t *>(slab_px)[q] = b[q];
-                }
+                for (int q = 0; q < K / 8; ++q)
+                    reinterpret_cast<uint2 *>(slab_px)[q] = make_uint2(b[2 * q], b[2 * q + 1]);
             } else {
 #pragma unroll
-                for (int q = 0; q < K / 2; ++q)
-                    reinterpret_cast<uint16_t *>(slab_px)[q] =
-                        (uint16_t)__builtin_amdgcn_perm(0u, L[q], 0x0c0c0200u);
+                for (int q = 0; q < K / 4; ++q) reinterpret_cast<uint32_t *>(slab_px)[q] = b[q];
             }
+        } else {
+#pragma unroll
+            for (int q = 0; q < K / 2; ++q)
+                reinterpret_cast<uint16_t *>(slab_px)[q] =
+                    (uint16_t)__builtin_amdgcn_perm(0u, L[q], 0x0c0c0200u);
         }
     }
-};
+}
 
 // Prefetch depth (steps) of the cost stream of one chain.
 constexpr int SGM_U = 8;
 
+// Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
+// cost: [H][W][D]; out_slab: this direction's [H][W][D] u8 slab (ATOMIC ==
+// false) or S [H][W][D] u16 (ATOMIC == true).
 template <int K, bool ATOMIC>
-__global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__restrict__ cost,
-                                                           int H, int W, int P1, int P2,
-                                                           PathTable tab, uint8_t *__restrict__ slab,
-                                                           uint16_t *__restrict__ S)
+__device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
+                                          uint16_t *__restrict__ S, int H, int W, int P1, int P2,
+                                          int r, int l, int j)
 {
     constexpr int D = 16 * K;
     constexpr int NP = K / 2;
-    const int g = blockIdx.x * SGM_CPB + (threadIdx.x >> 4);
-    const int j = threadIdx.x & 15;
-    if (g >= tab.off[tab.ndir]) return;
-    int k = 0;
-    while (g >= tab.off[k + 1]) ++k;
-    const int r = tab.dir[k];
-    const int l = g - tab.off[k];
     int x, y, len;
     chain_geometry(r, l, H, W, x, y, len);
     const int rx = c_dir[r][0], ry = c_dir[r][1];
-    const size_t npx = (size_t)H * W;
     const ptrdiff_t pstep = (ptrdiff_t)ry * W + rx;  // pixel-index step along the chain
-    size_t p = (size_t)y * W + x;
+    const ptrdiff_t p = (ptrdiff_t)y * W + x;
     const uint8_t *cbase = cost + (size_t)j * K;
-    uint8_t *sbase = ATOMIC ? nullptr : slab + (size_t)tab.slot[k] * npx * D + (size_t)j * K;
+    uint8_t *sbase = ATOMIC ? nullptr : slab + (size_t)j * K;
     uint16_t *Sbase = ATOMIC ? S + (size_t)j * K : nullptr;
 
     const u16x2 vP1 = (u16x2)((unsigned short)P1);
@@ -196,14 +187,14 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
 #pragma unroll
         for (int u = 0; u < SGM_U; ++u) {
             const int t = t0 + u;
-            if (t < len) load_raw<K>(cbase + (size_t)((ptrdiff_t)p + (ptrdiff_t)t * pstep) * D, buf[u]);
+            if (t < len) load_raw<K>(cbase + (size_t)(p + (ptrdiff_t)t * pstep) * D, buf[u]);
         }
     };
     auto step = [&](int t, const CostRaw<K> &raw) {
         if (t >= len) return;
         uint32_t c[NP];
         unpack<K>(raw, c);
-        const size_t pt = (size_t)((ptrdiff_t)p + (ptrdiff_t)t * pstep);
+        const size_t pt = (size_t)(p + (ptrdiff_t)t * pstep);
         if (t == 0) {
 #pragma unroll
             for (int i = 0; i < NP; ++i) L[i] = c[i];
@@ -228,7 +219,7 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
 #pragma unroll
             for (int i = 0; i < NP; ++i) L[i] = nL[i];
         }
-        Emit<K, ATOMIC>::run(L, ATOMIC ? nullptr : sbase + pt * D, ATOMIC ? Sbase + pt * D : nullptr);
+        emit<K, ATOMIC>(L, ATOMIC ? nullptr : sbase + pt * D, ATOMIC ? Sbase + pt * D : nullptr);
         u16x2 m2 = as_u16x2(L[0]);
 #pragma unroll
         for (int i = 1; i < NP; ++i) m2 = __builtin_elementwise_min(m2, as_u16x2(L[i]));
@@ -244,6 +235,65 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
         fetch(t0 + 2 * SGM_U, bufA);
 #pragma unroll
         for (int u = 0; u < SGM_U; ++u) step(t0 + SGM_U + u, bufB[u]);
+    }
+}
+
+// One view; block b, row q -> chain g = 16 b + q, mapped through the table.
+template <int K, bool ATOMIC>
+__global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__restrict__ cost,
+                                                           int H, int W, int P1, int P2,
+                                                           PathTable tab, uint8_t *__restrict__ slab,
+                                                           uint16_t *__restrict__ S)
+{
+    constexpr int D = 16 * K;
+    const int g = blockIdx.x * SGM_CPB + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (g >= tab.off[tab.ndir]) return;
+    int k = 0;
+    while (g >= tab.off[k + 1]) ++k;
+    const size_t npx = (size_t)H * W;
+    uint8_t *sl = ATOMIC ? nullptr : slab + (size_t)k * npx * D;
+    sgm_chain<K, ATOMIC>(cost, sl, S, H, W, P1, P2, tab.dir[k], g - tab.off[k], j);
+}
+
+// Many views from a task table.  persistent != 0: gridDim.x blocks pull task
+// indices from *counter (zeroed before the launch) until the table is done.
+__global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
+                                                           const AggTask *__restrict__ tasks,
+                                                           int ntasks, uint8_t *base,
+                                                           int *counter)
+{
+    __shared__ int s_task;
+    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
+    int ti = blockIdx.x;
+    for (;;) {
+        if (counter) {
+            if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
+            __syncthreads();
+            ti = s_task;
+            __syncthreads();
+        }
+        if (ti >= ntasks) return;
+        const AggTask tk = tasks[ti];
+        const AggView &v = views[tk.view];
+        if (q < tk.nlines) {
+            const uint8_t *cost = reinterpret_cast<const uint8_t *>((uintptr_t)base + v.cost_off);
+            uint8_t *slab = reinterpret_cast<uint8_t *>((uintptr_t)base + v.slab_off) +
+                            (size_t)tk.slot * v.H * v.W * (16 * v.K);
+            const int r = v.dir[tk.slot], l = tk.line0 + q;
+            switch (v.K) {
+            case 2: sgm_chain<2, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 4: sgm_chain<4, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 6: sgm_chain<6, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 8: sgm_chain<8, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 10: sgm_chain<10, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 12: sgm_chain<12, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 14: sgm_chain<14, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            case 16: sgm_chain<16, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
+            default: break;
+            }
+        }
+        if (!counter) return;
     }
 }
 
@@ -298,6 +348,75 @@ static void launch_paths(bool atomic, int nblk, hipStream_t st, const uint8_t *c
                            H, W, P1, P2, tab, slab, S);
 }
 
+// --- task tables (host) ------------------------------------------------------
+
+int chains_of(int r, int H, int W) { return r < 2 ? H : (r < 4 ? W : W + H - 1); }
+
+static int chain_len(int r, int l, int H, int W)
+{
+    if (r < 2) return W;
+    if (r < 4) return H;
+    // Diagonals: lines starting on the x edge (l < H) then on the y edge.
+    static const int d[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
+                                {+1, +1}, {-1, +1}, {+1, -1}, {-1, -1}};
+    const int rx = d[r][0], ry = d[r][1];
+    int x, y;
+    if (l < H) {
+        x = rx > 0 ? 0 : W - 1;
+        y = ry > 0 ? l : H - 1 - l;
+    } else {
+        const int k = l - H;
+        x = rx > 0 ? k + 1 : W - 2 - k;
+        y = ry > 0 ? 0 : H - 1;
+    }
+    const int nx = rx > 0 ? W - x : x + 1, ny = ry > 0 ? H - y : y + 1;
+    return nx < ny ? nx : ny;
+}
+
+void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, int view,
+                      const AggView &v)
+{
+    for (int s = 0; s < v.ndir; ++s) {
+        const int r = v.dir[s];
+        const int n = chains_of(r, v.H, v.W);
+        for (int l0 = 0; l0 < n; l0 += SGM_CPB) {
+            AggTask t{view, s, l0, n - l0 < SGM_CPB ? n - l0 : SGM_CPB};
+            int mx = 0;
+            for (int l = l0; l < l0 + t.nlines; ++l) mx = std::max(mx, chain_len(r, l, v.H, v.W));
+            tasks.push_back(t);
+            task_len.push_back(mx * v.K);
+        }
+    }
+}
+
+void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int> &task_len)
+{
+    std::vector<int> idx(tasks.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return task_len[a] > task_len[b]; });
+    std::vector<AggTask> out(tasks.size());
+    for (size_t i = 0; i < idx.size(); ++i) out[i] = tasks[idx[i]];
+    tasks.swap(out);
+}
+
+int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, uint8_t *base,
+                     int *d_counter, int persistent_blocks, hipStream_t st)
+{
+    if (ntasks <= 0) return SF_OK;
+    ProfScope prof("sgm_tasks", st);
+    if (persistent_blocks > 0) {
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st,
+                           reinterpret_cast<uint32_t *>(d_counter), (size_t)1, 0u);
+        int nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
+        hipLaunchKernelGGL(sgm_tasks_kernel, dim3(nb), dim3(SGM_NT), 0, st, d_views, d_tasks,
+                           ntasks, base, d_counter);
+    } else {
+        hipLaunchKernelGGL(sgm_tasks_kernel, dim3(ntasks), dim3(SGM_NT), 0, st, d_views, d_tasks,
+                           ntasks, base, (int *)nullptr);
+    }
+    return launch_status("sgm_tasks_kernel");
+}
+
 }  // namespace sf
 
 using namespace sf;
@@ -329,23 +448,17 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_sgm_aggregate: D must be in [1, 256]");
     SF_REQUIRE(D % 32 == 0, SF_EUNSUPPORTED,
                "sf_sgm_aggregate: these kernels need D to be a multiple of 32");
+    SF_REQUIRE((long long)H * W <= (1LL << 28), SF_EINVAL, "sf_sgm_aggregate: image too large");
     PathTable tab{};
     tab.off[0] = 0;
     for (int r = 0; r < 8; ++r) {
         if (!(path_mask & (1u << r))) continue;
         tab.dir[tab.ndir] = r;
-        tab.slot[tab.ndir] = tab.ndir;
         tab.off[tab.ndir + 1] = tab.off[tab.ndir] + chains_of(r, H, W);
         ++tab.ndir;
     }
     const size_t ncell = (size_t)H * W * D;
-    bool atomic;
-    if (g_epilogue_mode == 2)
-        atomic = true;
-    else if (g_epilogue_mode == 1)
-        atomic = false;
-    else
-        atomic = false;
+    bool atomic = g_epilogue_mode == 2;
     if (SF_CMAX + P2 > 255) atomic = true;  // Lr no longer fits a u8 slab
     const size_t need = atomic ? 0 : (size_t)tab.ndir * ncell;
     if (!atomic) {
@@ -364,18 +477,18 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     const int nchains = tab.off[tab.ndir];
     const int nblk = (nchains + SGM_CPB - 1) / SGM_CPB;
     {
-    ProfScope prof("sgm_paths", st);
-    switch (D / 16) {
-    case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 6: launch_paths<6>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 8: launch_paths<8>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 10: launch_paths<10>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 12: launch_paths<12>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 14: launch_paths<14>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-    default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
-    }
+        ProfScope prof("sgm_paths", st);
+        switch (D / 16) {
+        case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 6: launch_paths<6>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 8: launch_paths<8>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 10: launch_paths<10>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 12: launch_paths<12>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 14: launch_paths<14>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
+        }
     }
     int rc = launch_status("sgm_paths_kernel");
     if (rc || atomic) return rc;

@@ -1,0 +1,38 @@
+// Multi-view aggregation task tables (shared by the frame and batch paths).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+namespace sf {
+
+// One view to aggregate.  Pointers are base + offset, where base is a kernel
+// argument (the caller's workspace) so a table stays valid for any workspace
+// address when the offsets are relative, or base = 0 and offsets absolute.
+struct AggView {
+    uint64_t cost_off;  // cost volume [H][W][16 K] u8
+    uint64_t slab_off;  // ndir slabs [ndir][H][W][16 K] u8
+    int H, W, K;        // D = 16 K
+    int P1, P2;
+    int ndir;
+    int dir[8];         // direction of slab slot s
+};
+
+// Up to 16 consecutive chains (lines line0 ..) of one direction slot of a view.
+struct AggTask {
+    int view, slot, line0, nlines;
+};
+
+int chains_of(int r, int H, int W);
+void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, int view,
+                      const AggView &v);
+void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int> &task_len);
+// persistent_blocks > 0: persistent launch with that many blocks pulling from
+// *d_counter (reset on the stream first); 0: one block per task.
+int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, uint8_t *base,
+                     int *d_counter, int persistent_blocks, hipStream_t st);
+
+}  // namespace sf

@@ -1,0 +1,56 @@
+// Launch helpers of the per-pixel stages, each covering several images or
+// views of one size in one launch (the views travel in the kernel arguments).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sf.h"
+
+namespace sf {
+
+constexpr int STAGE_MAXV = 8;  // views per launch
+
+struct CensusArgs {
+    const uint8_t *img[STAGE_MAXV];
+    uint64_t *out[STAGE_MAXV];
+    int n, H, W, pitch;
+};
+
+struct CostArgs {
+    const uint64_t *base[STAGE_MAXV];
+    const uint64_t *match[STAGE_MAXV];
+    uint8_t *cost[STAGE_MAXV];
+    int right[STAGE_MAXV];
+    int n, H, W, D;
+};
+
+// WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8).
+// right_only: write d* to wta only.  Otherwise d*, sub-pixel disparity, the LR
+// check against wta_r (NULL: no check, valid := 1) and optional features.
+struct WtaView {
+    const uint8_t *slab;
+    const int16_t *wta_r;
+    const uint8_t *img;
+    int16_t *wta;
+    float *disp;
+    uint8_t *valid;
+    float *feat;
+    int nslab, H, W, D, P2, tol, pitch, right_only;
+};
+
+struct WtaArgs {
+    WtaView v[STAGE_MAXV];
+    int blk0[STAGE_MAXV + 1];  // first block of each view; blk0[n] = grid size
+    int n;
+};
+
+int launch_census(const CensusArgs &a, hipStream_t st);
+int launch_cost(const CostArgs &a, hipStream_t st);
+int launch_wta_slabs(WtaArgs &a, hipStream_t st);  // fills blk0
+int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
+                   const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
+                   float *sf4, uint8_t *valid, float *xyz0, float *motion, hipStream_t st);
+
+}  // namespace sf

@@ -7,6 +7,7 @@
 // c = j, j+16, ... (128 contiguous bytes per row per load), the (S, d) minimum
 // is a row butterfly on the key S * 512 + d, so ties go to the smallest d.
 #include "sf_internal.hpp"
+#include "stages.hpp"
 
 namespace sf {
 
@@ -100,6 +101,115 @@ __global__ __launch_bounds__(WTA_NT) void wta_left_kernel(
         f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
         reinterpret_cast<float4 *>(feat)[px] = f;
     }
+}
+
+// WTA on S = sum of u8 slabs, summed on the fly (S is never written).  Lane j
+// holds disparity chunks [8c, 8c + 8), c = j and j + 16, as packed u16 sums;
+// each slab load is 8 bytes per lane, 128 contiguous bytes per pixel row.
+__global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
+{
+    int vi = 0;
+    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
+    const WtaView v = a.v[vi];
+    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const int px = ((int)blockIdx.x - a.blk0[vi]) * WTA_PPB + q;
+    const int npx = v.H * v.W;
+    if (px >= npx) return;
+    const int D = v.D;
+    const size_t cells = (size_t)npx * D;
+    uint32_t sv[2][4];
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int c = j + 16 * i;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sv[i][e] = 0;
+        if (8 * c < D) {
+            const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
+            for (int k = 0; k < v.nslab; ++k) {
+                const uint2 w = *reinterpret_cast<const uint2 *>(src + (size_t)k * cells);
+                sv[i][0] += __builtin_amdgcn_perm(0u, w.x, 0x0c010c00u);
+                sv[i][1] += __builtin_amdgcn_perm(0u, w.x, 0x0c030c02u);
+                sv[i][2] += __builtin_amdgcn_perm(0u, w.y, 0x0c010c00u);
+                sv[i][3] += __builtin_amdgcn_perm(0u, w.y, 0x0c030c02u);
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
+                best = min(best, (val << 9) | (uint32_t)(8 * c + e));
+            }
+        }
+    }
+    const uint32_t key = row16_min(best);
+    const int ds = (int)(key & 511u);
+    const uint32_t smin = key >> 9;
+    if (v.right_only) {
+        if (j == 0) v.wta[px] = (int16_t)ds;
+        return;
+    }
+    uint32_t av = 0, cv = 0, s2 = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int c = j + 16 * i;
+        if (8 * c < D) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int d = 8 * c + e;
+                const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
+                if (d == ds - 1) av = val;
+                if (d == ds + 1) cv = val;
+                const int gap = d > ds ? d - ds : ds - d;
+                if (gap >= 2) s2 = min(s2, val);
+            }
+        }
+    }
+    av = row16_max(av);
+    cv = row16_max(cv);
+    s2 = row16_min(s2);
+    if (j != 0) return;
+    const int y = px / v.W, x = px - y * v.W;
+    float sub = (float)ds;
+    if (ds > 0 && ds < D - 1) {
+        const int den = (int)av - 2 * (int)smin + (int)cv;
+        if (den > 0) sub = (float)ds + (float)((int)av - (int)cv) / (float)(2 * den);
+    }
+    int ok = 1;
+    if (v.wta_r) {
+        const int qx = x - ds;
+        ok = 0;
+        if (qx >= 0) {
+            int diff = ds - (int)v.wta_r[(size_t)y * v.W + qx];
+            diff = diff < 0 ? -diff : diff;
+            ok = diff <= v.tol;
+        }
+    }
+    if (v.wta) v.wta[px] = (int16_t)ds;
+    v.disp[px] = ok ? sub : -1.0f;
+    v.valid[px] = (uint8_t)ok;
+    if (v.feat) {
+        if (s2 == 0xFFFFFFFFu) s2 = smin;
+        float4 f;
+        f.x = (float)v.img[(size_t)y * v.pitch + x] / 255.0f;
+        f.y = D > 1 ? (float)ds / (float)(D - 1) : 0.0f;
+        f.z = (float)smin / (float)(8 * (SF_CMAX + v.P2));
+        f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
+        reinterpret_cast<float4 *>(v.feat)[px] = f;
+    }
+}
+
+int launch_wta_slabs(WtaArgs &a, hipStream_t st)
+{
+    long long tot = 0;
+    for (int i = 0; i < a.n; ++i) {
+        a.blk0[i] = (int)tot;
+        tot += ((long long)a.v[i].H * a.v[i].W + WTA_PPB - 1) / WTA_PPB;
+    }
+    for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
+    if (tot <= 0) return SF_OK;
+    if (tot > 0x7FFFFFFFLL) return fail(SF_EINVAL, "launch_wta_slabs: grid too large");
+    ProfScope prof(a.v[0].right_only ? "wta_slab_right" : "wta_slab_left", st);
+    hipLaunchKernelGGL(wta_slab_kernel, dim3((unsigned)tot), dim3(WTA_NT), 0, st, a);
+    return launch_status("wta_slab_kernel");
 }
 
 }  // namespace sf

@@ -50,3 +50,25 @@ class PlainFrame:
         out = api.combine(m0["disp"], m0["valid"], m1["disp"], m1["valid"], flow, self.cam,
                           out=self.out)
         return m0, m1, out
+
+
+class FusedFrame:
+    """The same frame through the fused sf_frame_run entry point: six launches,
+    all four aggregations in one launch, S never materialised."""
+
+    def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
+                 cam=(721.5, 0.54, None, None), persistent: bool = False, device="cuda:0"):
+        self.H, self.W, self.D = H, W, D
+        f, B, cx, cy = cam
+        self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
+        self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent)
+        dev = torch.device(device)
+        e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
+        self.ws = e(self.plan.workspace_bytes(), dt=torch.uint8)
+        self.out = {"disp0": e(H, W, dt=torch.float32), "valid0": e(H, W, dt=torch.uint8),
+                    "disp1": e(H, W, dt=torch.float32), "valid1": e(H, W, dt=torch.uint8),
+                    "sf4": e(H, W, 4, dt=torch.float32), "valid": e(H, W, dt=torch.uint8),
+                    "xyz0": e(H, W, 3, dt=torch.float32), "motion": e(H, W, 3, dt=torch.float32)}
+
+    def run(self, L0, R0, L1, R1, flow):
+        return api.frame_run(self.plan, L0, R0, L1, R1, flow, self.cam, self.out, self.ws)

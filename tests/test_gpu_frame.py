@@ -1,0 +1,92 @@
+"""Whole scene-flow frames on the GPU against the CPU oracle: the fused frame
+entry point (all four aggregations in one launch, slabs summed inside WTA),
+its persistent variant, and the per-stage path, at a small size and at the
+full 1242x375 / D=128 size."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1801_04720_amd import synth  # noqa: E402
+from paper_1801_04720_amd.pipeline import FusedFrame, PlainFrame  # noqa: E402
+
+from gpu_util import DEV, assert_close_rel, dev, host  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_frame(orc, fr, D, cam):
+    w0, d0, v0 = orc.disparity(fr.t0.left, fr.t0.right, D)
+    w1, d1, v1 = orc.disparity(fr.t1.left, fr.t1.right, D)
+    sf4, valid, xyz0, motion = orc.combine(d0, v0, d1, v1, fr.flow, cam)
+    return dict(disp0=d0, valid0=v0, disp1=d1, valid1=v1, sf4=sf4, valid=valid, xyz0=xyz0, motion=motion)
+
+
+def check_frame(got, ref):
+    for k in ("valid0", "valid1", "valid"):
+        assert np.array_equal(host(got[k]), ref[k]), k
+    assert_close_rel(host(got["disp0"]), ref["disp0"], 1.0, what="disp0")
+    assert_close_rel(host(got["disp1"]), ref["disp1"], 1.0, what="disp1")
+    assert_close_rel(host(got["sf4"]), ref["sf4"], 1.0, what="sf4")
+    xyz0, motion = ref["xyz0"], ref["motion"]
+    P0 = np.linalg.norm(np.nan_to_num(xyz0), axis=-1, keepdims=True)
+    P1 = np.linalg.norm(np.nan_to_num(xyz0 + motion), axis=-1, keepdims=True)
+    assert_close_rel(host(got["xyz0"]), xyz0, np.maximum(P0, 1e-30), what="xyz0")
+    assert_close_rel(host(got["motion"]), motion, np.maximum(np.maximum(P0, P1), 1e-30), what="motion")
+
+
+@pytest.mark.parametrize("H,W,D,persistent", [(48, 160, 32, False), (61, 203, 64, True),
+                                              (40, 97, 96, False), (33, 300, 256, True)])
+def test_fused_frame_small(orc, H, W, D, persistent):
+    say("fused frame", H, W, D, persistent)
+    fr = synth.frame_planar(synth.rng_for(8, D), H, W, D, 20.0)
+    ff = FusedFrame(H, W, D, persistent=persistent, device=DEV)
+    got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
+    torch.cuda.synchronize()
+    check_frame(got, oracle_frame(orc, fr, D, ff.cam))
+
+
+def test_fused_frame_c2_vs_oracle(orc):
+    say("fused frame 1242x375 D=128 vs oracle")
+    fr = synth.frame_c2(0)
+    ff = FusedFrame(375, 1242, 128, device=DEV)
+    got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
+    torch.cuda.synchronize()
+    check_frame(got, oracle_frame(orc, fr, 128, ff.cam))
+
+
+def test_fused_equals_stagewise_and_persistent_c2():
+    say("fused vs per-stage vs persistent, 1242x375 D=128")
+    fr = synth.frame_c2(1)
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    a = FusedFrame(375, 1242, 128, device=DEV).run(*args)
+    a = {k: host(v).copy() for k, v in a.items()}
+    b = FusedFrame(375, 1242, 128, persistent=True, device=DEV).run(*args)
+    m0, m1, c = PlainFrame(375, 1242, 128, device=DEV).run(*args)
+    torch.cuda.synchronize()
+    for k in a:
+        assert np.array_equal(a[k], host(b[k]), equal_nan=True), k
+    assert np.array_equal(a["valid0"], host(m0["valid"]))
+    assert np.array_equal(a["disp1"], host(m1["disp"]))
+    for k in ("sf4", "valid", "xyz0", "motion"):
+        assert np.array_equal(a[k], host(c[k]), equal_nan=True), k
+
+
+def test_fused_frame_repeatable():
+    say("fused frame run twice")
+    fr = synth.frame_planar(synth.rng_for(8, 5), 64, 200, 64, 30.0)
+    ff = FusedFrame(64, 200, 64, persistent=True, device=DEV)
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    a = {k: host(v).copy() for k, v in ff.run(*args).items()}
+    b = {k: host(v).copy() for k, v in ff.run(*args).items()}
+    for k in a:
+        assert np.array_equal(a[k], b[k], equal_nan=True), k
