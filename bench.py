@@ -36,6 +36,27 @@ def kernel_ms(lib, name):
     return tot.value, n.value
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of the aggregation kernel from the committed counter
+    summary, only if the kernel sources are unchanged since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "sgm_tasks_frame_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if not kernel.startswith(rec["kernel"].split("<")[0][: len("sgm_tasks")]):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(fr, D):
     import oracle
 
@@ -60,6 +81,9 @@ def main():
                     help="fused: sf_frame_run; persistent: same with persistent aggregation "
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (the reference kernel "
+                         "for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -72,9 +96,19 @@ def main():
     from paper_1801_04720_amd import _lib, api, synth
     from paper_1801_04720_amd.pipeline import FusedFrame, PlainFrame
 
-    lib = _lib.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.copy_calibration:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty(n, dtype=torch.uint8, device=dev)
+        a.fill_(1)
+        for _ in range(max(args.steps, 1)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n, "launches": max(args.steps, 1)}), flush=True)
+        return
+    lib = _lib.lib()
     H, W, D = 375, 1242, 128
     fr = synth.frame_c2(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
@@ -118,7 +152,7 @@ def main():
     achieved = ops / avg_s / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": PEAK_U16_TOPS, "unit": "TOP/s (packed u16)",
-                "frac": achieved / PEAK_U16_TOPS, "traffic": None,
+                "frac": achieved / PEAK_U16_TOPS, "traffic": measured_traffic(kname),
                 "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"],
                 "gcups_per_launch": cells * views_per_launch / avg_s / 1e9}
     if args.pipeline == "stages":

@@ -92,8 +92,12 @@ __global__ __launch_bounds__(COST_NT) void cost_kernel(CostArgs a)
         const int qpp = D >> 2;  // 32-bit words per pixel
         const int nw = np * qpp;
         uint32_t *o32 = reinterpret_cast<uint32_t *>(out);
+        // Power-of-two words per pixel (D = 32, 64, 128, 256): shifts, no division.
+        const bool pow2 = (qpp & (qpp - 1)) == 0;
+        const int sh = __ffs(qpp) - 1;
         for (int j = threadIdx.x; j < nw; j += COST_NT) {
-            int p = j / qpp, d = (j - p * qpp) * 4;
+            const int p = pow2 ? (j >> sh) : j / qpp;
+            const int d = (j - p * qpp) * 4;
             uint32_t w = one(p, d) | (one(p, d + 1) << 8) | (one(p, d + 2) << 16) |
                          (one(p, d + 3) << 24);
             o32[j] = w;

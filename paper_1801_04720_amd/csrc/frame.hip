@@ -163,7 +163,8 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     rc = launch_cost(co, st);
     if (rc) return rc;
 
-    rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, ws, p->d_counter, p->persistent_blocks, st);
+    rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
+                          p->persistent_blocks, st);
     if (rc) return rc;
 
     int16_t *wtar[2], *wtal[2];

@@ -55,6 +55,8 @@ inline int launch_status(const char *kernel)
 // Device primitives.
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 __device__ __forceinline__ u16x2 as_u16x2(uint32_t u) { return __builtin_bit_cast(u16x2, u); }
@@ -82,22 +84,24 @@ __device__ __forceinline__ uint32_t dpp_fill(uint32_t fill, uint32_t v)
     return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, CTRL, 0xF, 0xF, false);
 }
 
-// Minimum over the 16 lanes of a row, left in every lane of the row.
+// Minimum over the 16 lanes of a row, left in every lane of the row.  The DPP
+// "old" operand is the identity of the reduction, which lets the compiler fold
+// each move into the min itself (v_min_u32_dpp).
 __device__ __forceinline__ uint32_t row16_min(uint32_t m)
 {
-    m = min(m, dpp<DPP_QUAD_XOR1>(m));
-    m = min(m, dpp<DPP_QUAD_XOR2>(m));
-    m = min(m, dpp<DPP_ROW_HALF_MIRROR>(m));
-    m = min(m, dpp<DPP_ROW_MIRROR>(m));
+    m = min(m, dpp_fill<DPP_QUAD_XOR1>(0xFFFFFFFFu, m));
+    m = min(m, dpp_fill<DPP_QUAD_XOR2>(0xFFFFFFFFu, m));
+    m = min(m, dpp_fill<DPP_ROW_HALF_MIRROR>(0xFFFFFFFFu, m));
+    m = min(m, dpp_fill<DPP_ROW_MIRROR>(0xFFFFFFFFu, m));
     return m;
 }
 
 __device__ __forceinline__ uint32_t row16_max(uint32_t m)
 {
-    m = max(m, dpp<DPP_QUAD_XOR1>(m));
-    m = max(m, dpp<DPP_QUAD_XOR2>(m));
-    m = max(m, dpp<DPP_ROW_HALF_MIRROR>(m));
-    m = max(m, dpp<DPP_ROW_MIRROR>(m));
+    m = max(m, dpp_fill<DPP_QUAD_XOR1>(0u, m));
+    m = max(m, dpp_fill<DPP_QUAD_XOR2>(0u, m));
+    m = max(m, dpp_fill<DPP_ROW_HALF_MIRROR>(0u, m));
+    m = max(m, dpp_fill<DPP_ROW_MIRROR>(0u, m));
     return m;
 }
 

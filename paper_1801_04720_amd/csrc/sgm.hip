@@ -134,18 +134,23 @@ __device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_p
 #pragma unroll
             for (int q = 0; q < K / 4; ++q)
                 b[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
+            // Slabs are written once and read once, much later: stream them past
+            // the caches (non-temporal) so the cost volumes stay cached.
             if constexpr (K % 16 == 0) {
 #pragma unroll
                 for (int q = 0; q < K / 16; ++q)
-                    reinterpret_cast<uint4 *>(slab_px)[q] =
-                        make_uint4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+                    __builtin_nontemporal_store(
+                        u32x4{b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]},
+                        reinterpret_cast<u32x4 *>(slab_px) + q);
             } else if constexpr (K % 8 == 0) {
 #pragma unroll
                 for (int q = 0; q < K / 8; ++q)
-                    reinterpret_cast<uint2 *>(slab_px)[q] = make_uint2(b[2 * q], b[2 * q + 1]);
+                    __builtin_nontemporal_store(u32x2{b[2 * q], b[2 * q + 1]},
+                                                reinterpret_cast<u32x2 *>(slab_px) + q);
             } else {
 #pragma unroll
-                for (int q = 0; q < K / 4; ++q) reinterpret_cast<uint32_t *>(slab_px)[q] = b[q];
+                for (int q = 0; q < K / 4; ++q)
+                    __builtin_nontemporal_store(b[q], reinterpret_cast<uint32_t *>(slab_px) + q);
             }
         } else {
 #pragma unroll
@@ -160,8 +165,8 @@ __device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_p
 constexpr int SGM_U = 8;
 
 // Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
-// cost: [H][W][D]; out_slab: this direction's [H][W][D] u8 slab (ATOMIC ==
-// false) or S [H][W][D] u16 (ATOMIC == true).
+// cost: [H][W][D]; slab: this direction's [H][W][D] u8 slab (ATOMIC == false)
+// or S [H][W][D] u16 (ATOMIC == true).
 template <int K, bool ATOMIC>
 __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
                                           uint16_t *__restrict__ S, int H, int W, int P1, int P2,
@@ -172,35 +177,37 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     int x, y, len;
     chain_geometry(r, l, H, W, x, y, len);
     const int rx = c_dir[r][0], ry = c_dir[r][1];
-    const ptrdiff_t pstep = (ptrdiff_t)ry * W + rx;  // pixel-index step along the chain
-    const ptrdiff_t p = (ptrdiff_t)y * W + x;
-    const uint8_t *cbase = cost + (size_t)j * K;
-    uint8_t *sbase = ATOMIC ? nullptr : slab + (size_t)j * K;
-    uint16_t *Sbase = ATOMIC ? S + (size_t)j * K : nullptr;
+    // Byte step along the chain in the [H][W][D] volumes.
+    const ptrdiff_t bstep = ((ptrdiff_t)ry * W + rx) * D;
+    const size_t b0 = ((size_t)y * W + x) * D + (size_t)j * K;
+    const uint8_t *ld = cost + b0;                               // next cost load
+    uint8_t *st = ATOMIC ? nullptr : slab + b0;                  // next slab store
+    uint16_t *stS = ATOMIC ? S + b0 : nullptr;                   // next S update
 
     const u16x2 vP1 = (u16x2)((unsigned short)P1);
     uint32_t L[NP];
     uint32_t M = 0;
+    // Loop-carried DPP destinations: the lanes with no source in the row (lane 0
+    // for row_shr, lane 15 for row_shl) keep the "no neighbour" value forever.
+    uint32_t below = SGM_SENT, above = SGM_SENT;
 
-    // Cost of the steps [t0, t0 + U) of this chain.
     auto fetch = [&](int t0, CostRaw<K>(&buf)[SGM_U]) {
 #pragma unroll
         for (int u = 0; u < SGM_U; ++u) {
-            const int t = t0 + u;
-            if (t < len) load_raw<K>(cbase + (size_t)(p + (ptrdiff_t)t * pstep) * D, buf[u]);
+            if (t0 + u < len) load_raw<K>(ld, buf[u]);
+            ld += bstep;
         }
     };
     auto step = [&](int t, const CostRaw<K> &raw) {
         if (t >= len) return;
         uint32_t c[NP];
         unpack<K>(raw, c);
-        const size_t pt = (size_t)(p + (ptrdiff_t)t * pstep);
         if (t == 0) {
 #pragma unroll
             for (int i = 0; i < NP; ++i) L[i] = c[i];
         } else {
-            const uint32_t below = dpp_fill<DPP_ROW_SHR1>(SGM_SENT, L[NP - 1]);
-            const uint32_t above = dpp_fill<DPP_ROW_SHL1>(SGM_SENT, L[0]);
+            below = dpp_fill<DPP_ROW_SHR1>(below, L[NP - 1]);
+            above = dpp_fill<DPP_ROW_SHL1>(above, L[0]);
             const u16x2 vM = (u16x2)((unsigned short)M);
             const u16x2 vMP2 = (u16x2)((unsigned short)(M + P2));
             uint32_t nL[NP];
@@ -219,7 +226,11 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
 #pragma unroll
             for (int i = 0; i < NP; ++i) L[i] = nL[i];
         }
-        emit<K, ATOMIC>(L, ATOMIC ? nullptr : sbase + pt * D, ATOMIC ? Sbase + pt * D : nullptr);
+        emit<K, ATOMIC>(L, st, stS);
+        if constexpr (ATOMIC)
+            stS += bstep;
+        else
+            st += bstep;
         u16x2 m2 = as_u16x2(L[0]);
 #pragma unroll
         for (int i = 1; i < NP; ++i) m2 = __builtin_elementwise_min(m2, as_u16x2(L[i]));
@@ -256,8 +267,10 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
     sgm_chain<K, ATOMIC>(cost, sl, S, H, W, P1, P2, tab.dir[k], g - tab.off[k], j);
 }
 
-// Many views from a task table.  persistent != 0: gridDim.x blocks pull task
-// indices from *counter (zeroed before the launch) until the table is done.
+// Many views from a task table (all tasks of one launch share K = D / 16).
+// persistent: gridDim.x blocks pull task indices from *counter (zeroed before
+// the launch) until the table is done; otherwise block b runs task b.
+template <int K>
 __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
                                                            const AggTask *__restrict__ tasks,
                                                            int ntasks, uint8_t *base,
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
         if (counter) {
             if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
             __syncthreads();
-            ti = s_task;
+            ti = __builtin_amdgcn_readfirstlane(s_task);
             __syncthreads();
         }
         if (ti >= ntasks) return;
@@ -279,19 +292,9 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
         if (q < tk.nlines) {
             const uint8_t *cost = reinterpret_cast<const uint8_t *>((uintptr_t)base + v.cost_off);
             uint8_t *slab = reinterpret_cast<uint8_t *>((uintptr_t)base + v.slab_off) +
-                            (size_t)tk.slot * v.H * v.W * (16 * v.K);
-            const int r = v.dir[tk.slot], l = tk.line0 + q;
-            switch (v.K) {
-            case 2: sgm_chain<2, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 4: sgm_chain<4, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 6: sgm_chain<6, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 8: sgm_chain<8, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 10: sgm_chain<10, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 12: sgm_chain<12, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 14: sgm_chain<14, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            case 16: sgm_chain<16, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, r, l, j); break;
-            default: break;
-            }
+                            (size_t)tk.slot * v.H * v.W * (16 * K);
+            sgm_chain<K, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
+                                tk.line0 + q, j);
         }
         if (!counter) return;
     }
@@ -399,20 +402,36 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
     tasks.swap(out);
 }
 
-int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, uint8_t *base,
-                     int *d_counter, int persistent_blocks, hipStream_t st)
+template <int K>
+static void launch_tasks_k(int nb, hipStream_t st, const AggView *v, const AggTask *t, int n,
+                           uint8_t *base, int *counter)
+{
+    hipLaunchKernelGGL((sgm_tasks_kernel<K>), dim3(nb), dim3(SGM_NT), 0, st, v, t, n, base, counter);
+}
+
+int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
+                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st)
 {
     if (ntasks <= 0) return SF_OK;
     ProfScope prof("sgm_tasks", st);
+    int nb = ntasks;
+    int *counter = nullptr;
     if (persistent_blocks > 0) {
         hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st,
                            reinterpret_cast<uint32_t *>(d_counter), (size_t)1, 0u);
-        int nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
-        hipLaunchKernelGGL(sgm_tasks_kernel, dim3(nb), dim3(SGM_NT), 0, st, d_views, d_tasks,
-                           ntasks, base, d_counter);
-    } else {
-        hipLaunchKernelGGL(sgm_tasks_kernel, dim3(ntasks), dim3(SGM_NT), 0, st, d_views, d_tasks,
-                           ntasks, base, (int *)nullptr);
+        nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
+        counter = d_counter;
+    }
+    switch (K) {
+    case 2: launch_tasks_k<2>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 4: launch_tasks_k<4>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 6: launch_tasks_k<6>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 8: launch_tasks_k<8>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 10: launch_tasks_k<10>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 12: launch_tasks_k<12>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 14: launch_tasks_k<14>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 16: launch_tasks_k<16>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    default: return fail(SF_EUNSUPPORTED, "launch_agg_tasks: unsupported K");
     }
     return launch_status("sgm_tasks_kernel");
 }

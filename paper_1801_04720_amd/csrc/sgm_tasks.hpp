@@ -32,7 +32,7 @@ void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, i
 void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int> &task_len);
 // persistent_blocks > 0: persistent launch with that many blocks pulling from
 // *d_counter (reset on the stream first); 0: one block per task.
-int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, uint8_t *base,
-                     int *d_counter, int persistent_blocks, hipStream_t st);
+int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
+                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st);
 
 }  // namespace sf

@@ -127,7 +127,8 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         if (8 * c < D) {
             const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
             for (int k = 0; k < v.nslab; ++k) {
-                const uint2 w = *reinterpret_cast<const uint2 *>(src + (size_t)k * cells);
+                const u32x2 w = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x2 *>(src + (size_t)k * cells));
                 sv[i][0] += __builtin_amdgcn_perm(0u, w.x, 0x0c010c00u);
                 sv[i][1] += __builtin_amdgcn_perm(0u, w.x, 0x0c030c02u);
                 sv[i][2] += __builtin_amdgcn_perm(0u, w.y, 0x0c010c00u);
