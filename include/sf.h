@@ -183,6 +183,41 @@ int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8
                  void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Learned stand-in for the left-right check (the check is the paper's, Sec.
+ * 3.1; the network is not: it predicts from the left view alone which pixels
+ * the check would keep, so the right-view aggregation can be skipped).
+ * Network: 3x3 cross-correlations with zero padding, channels 4 -> 16 -> 16 ->
+ * 16 -> 1, ReLU after the first three; layer inputs and weights rounded to
+ * BF16 (nearest even), biases FP32, FP32 sums; logit output.
+ * Parameters: flat FP32 vector of sf_lrnet_nparams() = 5377 values, W1[16][4][3][3]
+ * b1[16] W2[16][16][3][3] b2[16] W3[16][16][3][3] b3[16] W4[1][16][3][3] b4[1].
+ * Features: feat [B][H][W][4] FP32 as written by sf_wta_lr.
+ * workspace: sf_lrnet_workspace_bytes(B, H, W, train) bytes of device memory.
+ * Errors: SF_EINVAL (NULL, sizes), SF_ENOMEM (workspace). */
+int sf_lrnet_nparams(void);
+size_t sf_lrnet_workspace_bytes(int B, int H, int W, int train);
+/* logits [B][H][W] FP32 (output). */
+int sf_lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
+                     void *workspace, size_t ws_bytes, void *stream);
+/* Learned mask of one map: valid = logit > 0 and x - d* >= 0 (a match pixel
+ * outside the image can never pass the check); disp = d_sub where valid, else
+ * -1.0f.  wta [H][W] int16 d*, dsub [H][W] FP32. */
+int sf_lrnet_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
+                  uint8_t *valid, float *disp, void *stream);
+/* Mean binary cross-entropy of sigmoid(logit) against label [B][H][W] in {0,1}
+ * and its gradient: grad [5377] FP32 (output), loss [1] FP32 (output, device).
+ * Backward: dL/dz4 = (sigmoid(z4) - y)/N in FP32; BF16 rounding passed straight
+ * through; the gradients w.r.t. the pre-activations of layers 3..1 are rounded
+ * to BF16; weight and bias gradients are FP32 sums reduced in a fixed order
+ * (bit-reproducible run to run). */
+int sf_lrnet_grad(const float *params, const float *feat, const uint8_t *label, int B, int H, int W,
+                  float *grad, float *loss, void *workspace, size_t ws_bytes, void *stream);
+/* Adam in FP32, in place, in this order: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g g;
+ * w -= (lr m/(1-b1t)) / (sqrt(v/(1-b2t)) + eps); b1t, b2t = b1, b2 to the step count. */
+int sf_lrnet_adam(float *params, float *m, float *v, const float *grad, int n, float lr, float b1,
+                  float b2, float eps, float b1t, float b2t, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Kernel timer for benchmarking.  While enabled, each timed launch (census,
  * cost, sgm_paths, slab_sum, wta_right, wta_left, combine, ...) records a pair
  * of HIP events on its own stream; sf_prof_query waits for and sums those of one

@@ -48,6 +48,12 @@ SIGNATURES = {
     "sf_frame_plan_create": (I, [I, I, I, I, I, I, I, ct.POINTER(P)]),
     "sf_frame_run": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P, P, SZ,
                          P]),
+    "sf_lrnet_nparams": (I, []),
+    "sf_lrnet_workspace_bytes": (SZ, [I, I, I, I]),
+    "sf_lrnet_forward": (I, [P, P, I, I, I, P, P, SZ, P]),
+    "sf_lrnet_mask": (I, [P, P, P, I, I, P, P, P]),
+    "sf_lrnet_grad": (I, [P, P, P, I, I, I, P, P, P, SZ, P]),
+    "sf_lrnet_adam": (I, [P, P, P, P, I, F, F, F, F, F, F, P]),
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),

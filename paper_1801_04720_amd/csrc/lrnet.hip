@@ -1,0 +1,642 @@
+// Learned stand-in for the left-right consistency check.  The check itself is
+// the paper's (Sec. 3.1: comparing two computed disparity maps removes the
+// inconsistent pixels); this network predicts its outcome from the left view
+// alone so that the right-view aggregation can be skipped, and is trained on
+// labels produced by the check.
+//
+// Network: 3x3 convolutions (cross-correlation, zero padding), channels
+// 4 -> 16 -> 16 -> 16 -> 1, ReLU after the first three, logit output.  Layer
+// inputs and weights are BF16 (round to nearest even), biases FP32, sums FP32.
+// Flat FP32 parameter vector (5377): W1[16][4][3][3] b1[16] W2[16][16][3][3]
+// b2[16] W3[16][16][3][3] b3[16] W4[1][16][3][3] b4[1].
+//
+// Activations live in HBM as BF16 NHWC ([B][H][W][16], 32 bytes per pixel).
+// Kernels:
+//   l1_fwd     4 -> 16 (VALU: K = 36 is too thin for a matrix tile)
+//   conv16     16 -> 16 on MFMA v_mfma_f32_16x16x16_bf16: forward (bias,
+//              ReLU, BF16) or backward-data (transposed, flipped weights; the
+//              ReLU mask of the layer below; BF16)
+//   l4_fwd     16 -> 1 (VALU) + loss and dL/dz4 for training
+//   l4_bwd     dL/dz4 -> dL/dz3 (VALU) and the W4 / b4 partial gradients
+//   wgrad      dW[co][ci][tap] = sum_p gz[co](p) a[ci](p + tap - 1) on MFMA
+//              (K = pixels), per-block partials reduced in a fixed order
+//   adam       FP32 Adam step.
+#include "sf_internal.hpp"
+
+namespace sf {
+
+constexpr int LR_NP = 5377;
+constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 592, OFF_B2 = 2896, OFF_W3 = 2912, OFF_B3 = 5216,
+              OFF_W4 = 5232, OFF_B4 = 5376;
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ uint16_t bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u | ((u & 0x7fffffu) ? 0x400000u : 0u)) >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ float bf16_round(float f) { return bf16_val(bf16_bits(f)); }
+
+// --- layer 1: features (FP32, rounded to BF16 on load) -> a1 ------------------
+constexpr int T1 = 16;  // 16 x 16 output pixels per block
+
+__global__ __launch_bounds__(256) void l1_fwd_kernel(const float *__restrict__ prm,
+                                                     const float4 *__restrict__ feat, int H, int W,
+                                                     uint16_t *__restrict__ a1)
+{
+    __shared__ float s_in[T1 + 2][T1 + 2][4];
+    __shared__ float s_w[16][4][9];
+    __shared__ float s_b[16];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * T1, y0 = blockIdx.y * T1;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 576; i += 256) (&s_w[0][0][0])[i] = bf16_round(prm[OFF_W1 + i]);
+    if (tid < 16) s_b[tid] = prm[OFF_B1 + tid];
+    const size_t img = (size_t)b * H * W;
+    for (int i = tid; i < (T1 + 2) * (T1 + 2); i += 256) {
+        int ly = i / (T1 + 2), lx = i - ly * (T1 + 2);
+        int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) f = feat[img + (size_t)gy * W + gx];
+        s_in[ly][lx][0] = bf16_round(f.x);
+        s_in[ly][lx][1] = bf16_round(f.y);
+        s_in[ly][lx][2] = bf16_round(f.z);
+        s_in[ly][lx][3] = bf16_round(f.w);
+    }
+    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= W || y >= H) return;
+    uint32_t packed[8];
+#pragma unroll
+    for (int co = 0; co < 16; co += 2) {
+        float z[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int ci = 0; ci < 4; ++ci)
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx)
+                        acc = __builtin_fmaf(s_w[co + h][ci][ky * 3 + kx], s_in[ty + ky][tx + kx][ci], acc);
+            acc += s_b[co + h];
+            z[h] = acc > 0.0f ? acc : 0.0f;
+        }
+        packed[co / 2] = (uint32_t)bf16_bits(z[0]) | ((uint32_t)bf16_bits(z[1]) << 16);
+    }
+    uint4 *o = reinterpret_cast<uint4 *>(a1 + (img + (size_t)y * W + x) * 16);
+    o[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    o[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+}
+
+// --- 16 -> 16 convolution on MFMA ---------------------------------------------
+// Output tile 8 x 32 pixels = 16 groups of 16 consecutive pixels of a row; wave
+// w computes groups w, w+4, w+8, w+12.  For each group and tap one
+// v_mfma_f32_16x16x16_bf16 with
+//   A[m][k] = in[pixel m shifted by the tap][channel k]   (lane: m = l%16, k = 4(l/16)+i)
+//   B[k][n] = weight[tap][in channel k][out channel n]     (lane: n = l%16, k = 4(l/16)+i)
+//   D[m][n] accumulates in FP32                             (lane: n = l%16, m = 4(l/16)+i)
+constexpr int CT_H = 8, CT_W = 32;
+
+template <bool BWD>
+__global__ __launch_bounds__(256) void conv16_mfma_kernel(const float *__restrict__ prm, int w_off,
+                                                          int b_off, const uint16_t *__restrict__ in,
+                                                          const uint16_t *__restrict__ relu_src,
+                                                          int H, int W, uint16_t *__restrict__ out)
+{
+    __shared__ __align__(16) uint16_t s_in[CT_H + 2][CT_W + 2][16];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * CT_W, y0 = blockIdx.y * CT_H;
+    const int tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    // Stage the input tile with its 1-pixel halo (zeros outside the image).
+    for (int i = tid; i < (CT_H + 2) * (CT_W + 2) * 2; i += 256) {
+        const int px = i >> 1, half = i & 1;
+        const int ly = px / (CT_W + 2), lx = px - ly * (CT_W + 2);
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = reinterpret_cast<const uint4 *>(in + (img + (size_t)gy * W + gx) * 16)[half];
+        reinterpret_cast<uint4 *>(&s_in[ly][lx][0])[half] = v;
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 15, kg = lane >> 4;
+    // B fragments of the 9 taps.  Forward: B[k][n] = W[n][k][ky][kx].
+    // Backward-data: B[k][n] = W[k][n][2-ky][2-kx] (transpose and flip).
+    bf16x4 bw[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ky = t / 3, kx = t % 3;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * kg + i;
+            const int idx = BWD ? ((k * 16 + n) * 9 + (2 - ky) * 3 + (2 - kx)) : ((n * 16 + k) * 9 + t);
+            bw[t][i] = (short)bf16_bits(prm[w_off + idx]);
+        }
+    }
+    const float bias = BWD ? 0.0f : prm[b_off + n];
+    __syncthreads();
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi) {
+        const int g = wave + 4 * gi;
+        const int ty = g >> 1, tx0 = (g & 1) * 16;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&s_in[ty + ky][tx0 + n + kx][4 * kg]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t], acc, 0, 0, 0);
+        }
+        const int y = y0 + ty;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + tx0 + 4 * kg + i;
+            if (y >= H || x >= W) continue;
+            const size_t o = (img + (size_t)y * W + x) * 16 + n;
+            float v;
+            if (BWD) {
+                // Gradient w.r.t. the pre-activation of the layer below: pass only
+                // where its ReLU was active, then round to BF16.
+                v = bf16_val(relu_src[o]) > 0.0f ? acc[i] : 0.0f;
+            } else {
+                v = acc[i] + bias;
+                v = v > 0.0f ? v : 0.0f;
+            }
+            out[o] = bf16_bits(v);
+        }
+    }
+}
+
+// --- layer 4: 16 -> 1 ---------------------------------------------------------
+// One thread per pixel of a 16 x 16 tile.  Inference writes the logit; training
+// also writes g4 = (sigmoid(z) - y) / N and per-block partial losses.
+__global__ __launch_bounds__(256) void l4_fwd_kernel(const float *__restrict__ prm,
+                                                     const uint16_t *__restrict__ a3, int H, int W,
+                                                     float *__restrict__ logits,
+                                                     const uint8_t *__restrict__ label, float inv_n,
+                                                     float *__restrict__ g4,
+                                                     float *__restrict__ loss_part)
+{
+    __shared__ __align__(16) uint16_t s_in[T1 + 2][T1 + 2][16];
+    __shared__ float s_w[16][9];
+    __shared__ float s_red[256];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * T1, y0 = blockIdx.y * T1;
+    const int tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    for (int i = tid; i < 144; i += 256) (&s_w[0][0])[i] = bf16_round(prm[OFF_W4 + i]);
+    for (int i = tid; i < (T1 + 2) * (T1 + 2) * 2; i += 256) {
+        const int px = i >> 1, half = i & 1;
+        const int ly = px / (T1 + 2), lx = px - ly * (T1 + 2);
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = reinterpret_cast<const uint4 *>(a3 + (img + (size_t)gy * W + gx) * 16)[half];
+        reinterpret_cast<uint4 *>(&s_in[ly][lx][0])[half] = v;
+    }
+    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    const int x = x0 + tx, y = y0 + ty;
+    float l = 0.0f;
+    if (x < W && y < H) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int ci = 0; ci < 16; ++ci)
+#pragma unroll
+            for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                for (int kx = 0; kx < 3; ++kx)
+                    acc = __builtin_fmaf(s_w[ci][ky * 3 + kx], bf16_val(s_in[ty + ky][tx + kx][ci]), acc);
+        const float z = acc + prm[OFF_B4];
+        const size_t p = img + (size_t)y * W + x;
+        if (logits) logits[p] = z;
+        if (label) {
+            const float yv = label[p] ? 1.0f : 0.0f;
+            const float s = 1.0f / (1.0f + expf(-z));
+            g4[p] = (s - yv) * inv_n;
+            const float sp = z > 0.0f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+            l = sp - yv * z;
+        }
+    }
+    if (loss_part) {
+        s_red[tid] = l;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) s_red[tid] += s_red[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0)
+            loss_part[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = s_red[0];
+    }
+}
+
+// dL/dz3[q][ci] = bf16( sum_tap W4[ci][tap] g4(q - tap + 1) * [a3(q, ci) > 0] ), and the
+// W4 / b4 partial gradients sum_p g4(p) a3[ci](p + tap - 1), sum_p g4(p) of this tile.
+__global__ __launch_bounds__(256) void l4_bwd_kernel(const float *__restrict__ prm,
+                                                     const float *__restrict__ g4,
+                                                     const uint16_t *__restrict__ a3, int H, int W,
+                                                     uint16_t *__restrict__ gz3,
+                                                     float *__restrict__ part)
+{
+    __shared__ float s_g[T1 + 2][T1 + 2];
+    __shared__ __align__(16) uint16_t s_a[T1 + 2][T1 + 2][16];
+    __shared__ float s_w[16][9];
+    __shared__ float s_red[145][8];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * T1, y0 = blockIdx.y * T1;
+    const int tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    for (int i = tid; i < 144; i += 256) (&s_w[0][0])[i] = bf16_round(prm[OFF_W4 + i]);
+    for (int i = tid; i < (T1 + 2) * (T1 + 2); i += 256) {
+        const int ly = i / (T1 + 2), lx = i - ly * (T1 + 2);
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        const bool in_img = gy >= 0 && gy < H && gx >= 0 && gx < W;
+        s_g[ly][lx] = in_img ? g4[img + (size_t)gy * W + gx] : 0.0f;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a3 + (img + (size_t)gy * W + gx) * 16);
+        uint4 v0 = make_uint4(0u, 0u, 0u, 0u), v1 = v0;
+        if (in_img) { v0 = src[0]; v1 = src[1]; }
+        reinterpret_cast<uint4 *>(&s_a[ly][lx][0])[0] = v0;
+        reinterpret_cast<uint4 *>(&s_a[ly][lx][0])[1] = v1;
+    }
+    __syncthreads();
+    const int tx = tid & 15, ty = tid >> 4;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool inside = x < W && y < H;
+    if (inside) {
+        uint32_t packed[8];
+#pragma unroll
+        for (int ci = 0; ci < 16; ci += 2) {
+            float v[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float acc = 0.0f;
+#pragma unroll
+                for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+                    for (int kx = 0; kx < 3; ++kx)
+                        acc = __builtin_fmaf(s_w[ci + h][ky * 3 + kx], s_g[ty + 2 - ky][tx + 2 - kx], acc);
+                v[h] = bf16_val(s_a[ty + 1][tx + 1][ci + h]) > 0.0f ? acc : 0.0f;
+            }
+            packed[ci / 2] = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+        }
+        uint4 *o = reinterpret_cast<uint4 *>(gz3 + (img + (size_t)y * W + x) * 16);
+        o[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+        o[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+    }
+    // Partial weight gradients: thread handles parameter i = tid (< 145), summing
+    // over the tile's 256 pixels in a fixed order.
+    if (tid < 145) {
+        float acc = 0.0f;
+        if (tid < 144) {
+            const int ci = tid / 9, t = tid % 9, ky = t / 3, kx = t % 3;
+            for (int p = 0; p < 256; ++p) {
+                const int py = p >> 4, pxl = p & 15;
+                acc = __builtin_fmaf(s_g[py + 1][pxl + 1], bf16_val(s_a[py + ky][pxl + kx][ci]), acc);
+            }
+        } else {
+            for (int p = 0; p < 256; ++p) acc += s_g[(p >> 4) + 1][(p & 15) + 1];
+        }
+        const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        part[blk * 145 + tid] = acc;
+    }
+}
+
+// --- weight gradients of a 16-output layer on MFMA ------------------------------
+// dW[co][ci][tap] = sum_p gz[co](p) a[ci](p + tap - 1), db[co] = sum_p gz[co](p)
+// over a tile of 8 x 32 pixels; CIN = 16 (a = BF16 NHWC16 activations) or 4
+// (a = FP32 features, rounded to BF16, padded to 16 channels with zeros).
+// MFMA: M = co, N = ci, K = 16 pixels of one tile row half; each wave takes 4 of
+// the 16 pixel groups and all 9 taps; the 4 waves' sums are added in order.
+template <int CIN>
+__global__ __launch_bounds__(256) void wgrad_mfma_kernel(const uint16_t *__restrict__ gz,
+                                                         const uint16_t *__restrict__ a16,
+                                                         const float4 *__restrict__ a4, int H,
+                                                         int W, float *__restrict__ part)
+{
+    constexpr int NPART = 16 * CIN * 9 + 16;
+    __shared__ __align__(16) uint16_t s_a[CT_H + 2][CT_W + 2][16];
+    __shared__ __align__(16) uint16_t s_g[CT_H][CT_W][16];
+    __shared__ float s_acc[4][9][4][64];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * CT_W, y0 = blockIdx.y * CT_H;
+    const int tid = threadIdx.x;
+    const size_t img = (size_t)b * H * W;
+    for (int i = tid; i < (CT_H + 2) * (CT_W + 2) * 2; i += 256) {
+        const int px = i >> 1, half = i & 1;
+        const int ly = px / (CT_W + 2), lx = px - ly * (CT_W + 2);
+        const int gy = y0 + ly - 1, gx = x0 + lx - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            if (CIN == 16) {
+                v = reinterpret_cast<const uint4 *>(a16 + (img + (size_t)gy * W + gx) * 16)[half];
+            } else if (half == 0) {
+                const float4 f = a4[img + (size_t)gy * W + gx];
+                v.x = (uint32_t)bf16_bits(f.x) | ((uint32_t)bf16_bits(f.y) << 16);
+                v.y = (uint32_t)bf16_bits(f.z) | ((uint32_t)bf16_bits(f.w) << 16);
+            }
+        }
+        reinterpret_cast<uint4 *>(&s_a[ly][lx][0])[half] = v;
+    }
+    for (int i = tid; i < CT_H * CT_W * 2; i += 256) {
+        const int px = i >> 1, half = i & 1;
+        const int ly = px / CT_W, lx = px - ly * CT_W;
+        const int gy = y0 + ly, gx = x0 + lx;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gy < H && gx < W) v = reinterpret_cast<const uint4 *>(gz + (img + (size_t)gy * W + gx) * 16)[half];
+        reinterpret_cast<uint4 *>(&s_g[ly][lx][0])[half] = v;
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6;
+    const int mn = lane & 15, kg = lane >> 4;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.0f;
+#pragma unroll
+    for (int gi = 0; gi < 4; ++gi) {
+        const int g = wave + 4 * gi;
+        const int ty = g >> 1, tx0 = (g & 1) * 16;
+        // A[m = co][k = pixel]: lane holds co = mn, pixels 4 kg + i of the group.
+        bf16x4 av;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = (short)s_g[ty][tx0 + 4 * kg + i][mn];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) dbias += bf16_val((uint16_t)av[i]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            // B[k = pixel][n = ci]: lane holds ci = mn, pixels 4 kg + i, shifted by the tap.
+            bf16x4 bv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bv[i] = (short)s_a[ty + ky][tx0 + 4 * kg + i + kx][mn];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+        }
+    }
+    // D[m = co][n = ci]: lane holds ci = mn, co = 4 kg + i.
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_acc[wave][t][i][lane] = acc[t][i];
+    __syncthreads();
+    const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float *pp = part + blk * NPART;
+    for (int e = tid; e < 16 * CIN * 9; e += 256) {
+        const int co = e / (CIN * 9), rem = e - co * CIN * 9, ci = rem / 9, t = rem % 9;
+        const int i = co & 3, kgo = co >> 2;
+        const int l = kgo * 16 + ci;
+        pp[e] = ((s_acc[0][t][i][l] + s_acc[1][t][i][l]) + s_acc[2][t][i][l]) + s_acc[3][t][i][l];
+    }
+    // Bias: lanes with the same co (= mn) across kg and waves.
+    __syncthreads();
+    float *s_db = &s_acc[0][0][0][0];
+    s_db[tid] = dbias;  // tid = wave * 64 + kg * 16 + co
+    __syncthreads();
+    if (tid < 16) {
+        float s = 0.0f;
+        for (int w = 0; w < 4; ++w)
+            for (int k = 0; k < 4; ++k) s += s_db[w * 64 + k * 16 + tid];
+        pp[16 * CIN * 9 + tid] = s;
+    }
+}
+
+// Sum over blocks, in block order, of the partial gradients part[blk][e]; slot
+// e < nw is weight woff + e, the rest biases boff + (e - nw).
+__global__ void reduce_parts_kernel(const float *__restrict__ part, int nblk, int npart, int nw,
+                                    int woff, int boff, float *__restrict__ grad)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npart) return;
+    float s = 0.0f;
+    for (int bk = 0; bk < nblk; ++bk) s += part[(size_t)bk * npart + e];
+    grad[e < nw ? woff + e : boff + (e - nw)] = s;
+}
+
+__global__ void sum_kernel(const float *__restrict__ v, int n, float scale, float *__restrict__ out)
+{
+    __shared__ float s[256];
+    float acc = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s[threadIdx.x] += s[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = s[0] * scale;
+}
+
+__global__ void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                            const float *__restrict__ g, int n, float lr, float b1, float b2,
+                            float eps, float b1t, float b2t)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * (gi * gi);
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - b1t);
+    const float vh = vi / (1.0f - b2t);
+    w[i] = w[i] - (lr * mh) / (sqrtf(vh) + eps);
+}
+
+// Learned mask: valid iff the logit is positive and x - d* >= 0 (a match pixel
+// outside the image can never pass the check); disp = d_sub where valid, else -1.
+__global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *__restrict__ wta,
+                               const float *__restrict__ dsub, int H, int W,
+                               uint8_t *__restrict__ valid, float *__restrict__ disp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H * W) return;
+    const int x = i % W;
+    const int ok = logits[i] > 0.0f && x - (int)wta[i] >= 0;
+    valid[i] = (uint8_t)ok;
+    disp[i] = ok ? dsub[i] : -1.0f;
+}
+
+// --- workspace layout -------------------------------------------------------------
+struct LrLayout {
+    size_t a1, a2, a3, z, g4, gz3, gz2, gz1, part, loss, total;
+    int nb4, nbc, npart_max;
+};
+
+static size_t al(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static LrLayout lr_layout(int B, int H, int W, bool train)
+{
+    LrLayout L{};
+    const size_t npx = (size_t)B * H * W;
+    const int nb4 = B * ((W + T1 - 1) / T1) * ((H + T1 - 1) / T1);
+    const int nbc = B * ((W + CT_W - 1) / CT_W) * ((H + CT_H - 1) / CT_H);
+    L.nb4 = nb4;
+    L.nbc = nbc;
+    size_t o = 0;
+    L.a1 = o; o += al(npx * 32);
+    L.a2 = o; o += al(npx * 32);
+    L.a3 = o; o += al(npx * 32);
+    L.z = o; o += al(npx * 4);
+    if (train) {
+        L.g4 = o; o += al(npx * 4);
+        L.gz3 = o; o += al(npx * 32);
+        L.gz2 = o; o += al(npx * 32);
+        L.gz1 = o; o += al(npx * 32);
+        const size_t p4 = (size_t)nb4 * 145, p16 = (size_t)nbc * (16 * 16 * 9 + 16);
+        L.part = o; o += al((p4 > p16 ? p4 : p16) * 4);
+        L.loss = o; o += al((size_t)nb4 * 4);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_lrnet_nparams(void) { return LR_NP; }
+
+extern "C" size_t sf_lrnet_workspace_bytes(int B, int H, int W, int train)
+{
+    if (B <= 0 || H <= 0 || W <= 0) return 0;
+    return lr_layout(B, H, W, train != 0).total;
+}
+
+static int lr_check(const float *params, const float *feat, int B, int H, int W, void *ws,
+                    size_t ws_bytes, bool train)
+{
+    SF_REQUIRE(params && feat && ws, SF_EINVAL, "sf_lrnet: NULL pointer");
+    SF_REQUIRE(B > 0 && H > 0 && W > 0, SF_EINVAL, "sf_lrnet: B, H, W must be positive");
+    SF_REQUIRE(B <= 65535 && (long long)B * H * W <= (1LL << 30), SF_EINVAL, "sf_lrnet: batch too large");
+    SF_REQUIRE(ws_bytes >= lr_layout(B, H, W, train).total, SF_ENOMEM, "sf_lrnet: workspace too small");
+    return SF_OK;
+}
+
+static int lr_forward(const float *params, const float *feat, int B, int H, int W, uint8_t *ws,
+                      const LrLayout &L, float *logits, const uint8_t *label, float *g4,
+                      float *loss_part, hipStream_t st)
+{
+    uint16_t *a1 = reinterpret_cast<uint16_t *>(ws + L.a1);
+    uint16_t *a2 = reinterpret_cast<uint16_t *>(ws + L.a2);
+    uint16_t *a3 = reinterpret_cast<uint16_t *>(ws + L.a3);
+    dim3 g1((W + T1 - 1) / T1, (H + T1 - 1) / T1, B);
+    dim3 gc((W + CT_W - 1) / CT_W, (H + CT_H - 1) / CT_H, B);
+    {
+        ProfScope prof("lrnet_l1", st);
+        hipLaunchKernelGGL(l1_fwd_kernel, g1, dim3(256), 0, st, params,
+                           reinterpret_cast<const float4 *>(feat), H, W, a1);
+    }
+    {
+        ProfScope prof("lrnet_conv16", st);
+        hipLaunchKernelGGL(conv16_mfma_kernel<false>, gc, dim3(256), 0, st, params, OFF_W2, OFF_B2,
+                           a1, (const uint16_t *)nullptr, H, W, a2);
+        hipLaunchKernelGGL(conv16_mfma_kernel<false>, gc, dim3(256), 0, st, params, OFF_W3, OFF_B3,
+                           a2, (const uint16_t *)nullptr, H, W, a3);
+    }
+    const float inv_n = 1.0f / (float)((double)B * H * W);
+    {
+        ProfScope prof("lrnet_l4", st);
+        hipLaunchKernelGGL(l4_fwd_kernel, g1, dim3(256), 0, st, params, a3, H, W, logits, label,
+                           inv_n, g4, loss_part);
+    }
+    return launch_status("lrnet forward");
+}
+
+extern "C" int sf_lrnet_forward(const float *params, const float *feat, int B, int H, int W,
+                                float *logits, void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = lr_check(params, feat, B, H, W, workspace, ws_bytes, false);
+    if (rc) return rc;
+    SF_REQUIRE(logits, SF_EINVAL, "sf_lrnet_forward: NULL logits");
+    const LrLayout L = lr_layout(B, H, W, false);
+    return lr_forward(params, feat, B, H, W, static_cast<uint8_t *>(workspace), L, logits, nullptr,
+                      nullptr, nullptr, as_stream(stream));
+}
+
+extern "C" int sf_lrnet_mask(const float *logits, const int16_t *wta, const float *dsub, int H,
+                             int W, uint8_t *valid, float *disp, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(logits && wta && dsub && valid && disp, SF_EINVAL, "sf_lrnet_mask: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0 && (long long)H * W <= (1LL << 30), SF_EINVAL, "sf_lrnet_mask: bad size");
+    const int n = H * W;
+    ProfScope prof("lrnet_mask", as_stream(stream));
+    hipLaunchKernelGGL(lr_mask_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), logits,
+                       wta, dsub, H, W, valid, disp);
+    return launch_status("lr_mask_kernel");
+}
+
+extern "C" int sf_lrnet_grad(const float *params, const float *feat, const uint8_t *label, int B,
+                             int H, int W, float *grad, float *loss, void *workspace,
+                             size_t ws_bytes, void *stream)
+{
+    clear_error();
+    int rc = lr_check(params, feat, B, H, W, workspace, ws_bytes, true);
+    if (rc) return rc;
+    SF_REQUIRE(label && grad && loss, SF_EINVAL, "sf_lrnet_grad: NULL pointer");
+    hipStream_t st = as_stream(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    const LrLayout L = lr_layout(B, H, W, true);
+    float *z = reinterpret_cast<float *>(ws + L.z);
+    float *g4 = reinterpret_cast<float *>(ws + L.g4);
+    float *lossp = reinterpret_cast<float *>(ws + L.loss);
+    rc = lr_forward(params, feat, B, H, W, ws, L, z, label, g4, lossp, st);
+    if (rc) return rc;
+    uint16_t *a1 = reinterpret_cast<uint16_t *>(ws + L.a1);
+    uint16_t *a2 = reinterpret_cast<uint16_t *>(ws + L.a2);
+    uint16_t *a3 = reinterpret_cast<uint16_t *>(ws + L.a3);
+    uint16_t *gz3 = reinterpret_cast<uint16_t *>(ws + L.gz3);
+    uint16_t *gz2 = reinterpret_cast<uint16_t *>(ws + L.gz2);
+    uint16_t *gz1 = reinterpret_cast<uint16_t *>(ws + L.gz1);
+    float *part = reinterpret_cast<float *>(ws + L.part);
+    dim3 g1((W + T1 - 1) / T1, (H + T1 - 1) / T1, B);
+    dim3 gc((W + CT_W - 1) / CT_W, (H + CT_H - 1) / CT_H, B);
+    ProfScope prof("lrnet_bwd", st);
+    // Layer 4.
+    hipLaunchKernelGGL(l4_bwd_kernel, g1, dim3(256), 0, st, params, g4, a3, H, W, gz3, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(1), dim3(256), 0, st, part, L.nb4, 145, 144,
+                       OFF_W4, OFF_B4, grad);
+    // Layer 3: weight gradient, then the gradient w.r.t. the layer-2 pre-activation.
+    hipLaunchKernelGGL(wgrad_mfma_kernel<16>, gc, dim3(256), 0, st, gz3, a2, (const float4 *)nullptr,
+                       H, W, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(10), dim3(256), 0, st, part, L.nbc, 2320, 2304,
+                       OFF_W3, OFF_B3, grad);
+    hipLaunchKernelGGL(conv16_mfma_kernel<true>, gc, dim3(256), 0, st, params, OFF_W3, 0, gz3, a2, H,
+                       W, gz2);
+    // Layer 2.
+    hipLaunchKernelGGL(wgrad_mfma_kernel<16>, gc, dim3(256), 0, st, gz2, a1, (const float4 *)nullptr,
+                       H, W, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(10), dim3(256), 0, st, part, L.nbc, 2320, 2304,
+                       OFF_W2, OFF_B2, grad);
+    hipLaunchKernelGGL(conv16_mfma_kernel<true>, gc, dim3(256), 0, st, params, OFF_W2, 0, gz2, a1, H,
+                       W, gz1);
+    // Layer 1 (the features are the layer input).
+    hipLaunchKernelGGL(wgrad_mfma_kernel<4>, gc, dim3(256), 0, st, gz1, (const uint16_t *)nullptr,
+                       reinterpret_cast<const float4 *>(feat), H, W, part);
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(3), dim3(256), 0, st, part, L.nbc, 592, 576,
+                       OFF_W1, OFF_B1, grad);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, lossp, L.nb4,
+                       1.0f / (float)((double)B * H * W), loss);
+    return launch_status("lrnet backward");
+}
+
+extern "C" int sf_lrnet_adam(float *params, float *m, float *v, const float *grad, int n, float lr,
+                             float b1, float b2, float eps, float b1t, float b2t, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(params && m && v && grad, SF_EINVAL, "sf_lrnet_adam: NULL pointer");
+    SF_REQUIRE(n > 0, SF_EINVAL, "sf_lrnet_adam: n <= 0");
+    SF_REQUIRE(b1t < 1.0f && b2t < 1.0f, SF_EINVAL, "sf_lrnet_adam: b1t, b2t must be < 1");
+    ProfScope prof("lrnet_adam", as_stream(stream));
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), params,
+                       m, v, grad, n, lr, b1, b2, eps, b1t, b2t);
+    return launch_status("adam_kernel");
+}

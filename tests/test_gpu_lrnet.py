@@ -1,0 +1,177 @@
+"""The learned LR stand-in on the GPU against the CPU oracle: exact logits on a
+dyadic grid (every FP32 sum exact, so summation order cannot matter), close
+logits and gradients on random data, bit-exact Adam, run-to-run determinism,
+checkpoint/resume, and a short training run that beats the method without
+the network."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1801_04720_amd import api, lrnet, synth  # noqa: E402
+from paper_1801_04720_amd.pipeline import FusedFrame  # noqa: E402
+
+from gpu_util import DEV, dev, host  # noqa: E402
+
+NP = 5377
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dyadic_setup(rng, B, H, W):
+    feat = (rng.integers(0, 17, (B, H, W, 4)) / 16.0).astype(np.float32)
+    prm = (rng.integers(-4, 5, NP) / 16.0).astype(np.float32)
+    for off in (576, 2896, 5216):
+        prm[off:off + 16] = rng.integers(-64, 257, 16) / 256.0
+    prm[5376] = rng.integers(-256, 257) / 256.0
+    return feat, prm
+
+
+@pytest.mark.parametrize("B,H,W", [(1, 8, 8), (2, 19, 45), (1, 33, 70)])
+def test_forward_exact_on_dyadic_grid(orc, B, H, W):
+    say("lrnet exact forward", B, H, W)
+    rng = np.random.default_rng(B * 100 + H)
+    feat, prm = dyadic_setup(rng, B, H, W)
+    got = host(lrnet.forward(dev(prm), dev(feat)))
+    _, ref, _ = orc.lrnet(feat, prm)
+    assert np.array_equal(got, ref)
+
+
+def test_forward_close_random(orc):
+    say("lrnet random forward")
+    rng = np.random.default_rng(3)
+    B, H, W = 2, 37, 53
+    feat = rng.uniform(0, 2, (B, H, W, 4)).astype(np.float32)
+    prm = lrnet.init_params(1)
+    got = host(lrnet.forward(dev(prm), dev(feat)))
+    _, ref, _ = orc.lrnet(feat, prm)
+    err = np.abs(got - ref)
+    # FP32 sums in another order can flip a BF16 rounding of an intermediate by one
+    # unit (2^-8 relative); the logits stay within a small fraction of their scale.
+    assert np.quantile(err, 0.99) <= 1e-3 * (1 + np.abs(ref).max())
+    assert err.max() <= 2e-2 * (1 + np.abs(ref).max())
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a.astype(np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_vs_oracle(orc, seed):
+    say("lrnet gradient", seed)
+    rng = np.random.default_rng(10 + seed)
+    B, H, W = 2, 24, 40
+    feat = rng.uniform(0, 1.5, (B, H, W, 4)).astype(np.float32)
+    label = (rng.uniform(size=(B, H, W)) < 0.8).astype(np.uint8)
+    prm = lrnet.init_params(seed)
+    prm[5376] = 0.3
+    g, loss = lrnet.grad(dev(prm), dev(feat), dev(label))
+    g = host(g)
+    ref_loss, _, ref = orc.lrnet(feat, prm, label, want_grad=True)
+    assert abs(float(host(loss)[0]) - ref_loss) <= 1e-5 * max(1.0, abs(ref_loss))
+    assert rel_err(g, ref) < 1e-2
+    for name, a, b in [("W1", 0, 576), ("b1", 576, 592), ("W2", 592, 2896), ("b2", 2896, 2912),
+                       ("W3", 2912, 5216), ("b3", 5216, 5232), ("W4", 5232, 5376), ("b4", 5376, 5377)]:
+        assert rel_err(g[a:b], ref[a:b]) < 2e-2, name
+
+
+def test_gradient_deterministic():
+    say("lrnet gradient twice")
+    rng = np.random.default_rng(4)
+    feat = dev(rng.uniform(0, 1, (3, 40, 70, 4)).astype(np.float32))
+    label = dev((rng.uniform(size=(3, 40, 70)) < 0.7).astype(np.uint8))
+    prm = dev(lrnet.init_params(2))
+    g1, l1 = lrnet.grad(prm, feat, label)
+    a1, b1 = host(g1).copy(), host(l1).copy()
+    g2, l2 = lrnet.grad(prm, feat, label)
+    assert np.array_equal(a1, host(g2)) and np.array_equal(b1, host(l2))
+
+
+def test_adam_bit_exact(orc):
+    say("adam")
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(NP).astype(np.float32)
+    m = (rng.standard_normal(NP) * 0.01).astype(np.float32)
+    v = (rng.uniform(0, 1e-3, NP)).astype(np.float32)
+    g = rng.standard_normal(NP).astype(np.float32)
+    tw, tm, tv = dev(w), dev(m), dev(v)
+    lrnet.adam(tw, tm, tv, dev(g), 1e-3, 0.9, 0.999, 1e-8, 7)
+    orc.adam(w, m, v, g, 1e-3, 0.9, 0.999, 1e-8, 7)
+    assert np.array_equal(host(tw), w) and np.array_equal(host(tm), m) and np.array_equal(host(tv), v)
+
+
+def test_mask_rule():
+    say("lrnet mask")
+    H, W = 3, 6
+    logits = np.array([[1, -1, 2, 0.5, -0.1, 3]] * H, np.float32)
+    wta = np.array([[0, 0, 3, 1, 0, 6]] * H, np.int16)
+    dsub = wta.astype(np.float32) + 0.25
+    valid, disp = lrnet.mask(dev(logits), dev(wta), dev(dsub))
+    # x - d* >= 0 and logit > 0
+    assert list(host(valid)[0]) == [1, 0, 0, 1, 0, 0]
+    assert list(host(disp)[0]) == [0.25, -1.0, -1.0, 1.25, -1.0, -1.0]
+
+
+def make_training_data(n_pairs, H, W, D, seed0):
+    """Features and plain-LR labels of t0 pairs, produced by the GPU plain path."""
+    feats, labels, wtas = [], [], []
+    for i in range(n_pairs):
+        p = synth.pair_planar(synth.rng_for(4, seed0 + i), H, W, D)
+        L, R = dev(p.left), dev(p.right)
+        cl, cr = api.census(L), api.census(R)
+        Sr = api.sgm_aggregate(api.cost(cr, cl, D, True), 10, 120)
+        Sl = api.sgm_aggregate(api.cost(cl, cr, D, False), 10, 120)
+        out = api.wta_lr(Sl, Sr, L, 120, 1, want_feat=True)
+        feats.append(out["feat"])
+        labels.append(out["valid"])
+        wtas.append(out["wta_left"])
+    return torch.stack(feats), torch.stack(labels), torch.stack(wtas)
+
+
+def test_training_beats_method_without_network():
+    say("lrnet training")
+    H, W, D = 96, 320, 64
+    feat, label, wta = make_training_data(12, H, W, D, 0)
+    vfeat, vlabel, vwta = make_training_data(3, H, W, D, 1000)
+    tr = lrnet.Trainer(lrnet.init_params(0), lr=3e-3)
+    losses = []
+    for step in range(300):
+        i = step % 3
+        losses.append(float(tr.step(feat[4 * i:4 * i + 4], label[4 * i:4 * i + 4]).item()))
+    assert np.mean(losses[-20:]) < 0.7 * np.mean(losses[:5])
+    logits = lrnet.forward(tr.params, vfeat)
+    lab = host(vlabel).astype(bool)
+    xs = np.arange(W)[None, None, :]
+    geo = (xs - host(vwta).astype(np.int64)) >= 0
+    learned = (host(logits) > 0) & geo
+    acc_none = (lab == np.ones_like(lab)).mean()
+    acc_geo = (lab == geo).mean()
+    acc_learned = (lab == learned).mean()
+    say(f"agreement: no check {acc_none:.4f}, geometric rule {acc_geo:.4f}, learned {acc_learned:.4f}")
+    assert acc_learned > acc_geo >= acc_none
+
+
+def test_checkpoint_resume_bit_exact():
+    say("lrnet checkpoint")
+    rng = np.random.default_rng(9)
+    feat = dev(rng.uniform(0, 1, (2, 32, 48, 4)).astype(np.float32))
+    label = dev((rng.uniform(size=(2, 32, 48)) < 0.8).astype(np.uint8))
+    a = lrnet.Trainer(lrnet.init_params(3))
+    for _ in range(5):
+        a.step(feat, label)
+    st = a.state()
+    b = lrnet.Trainer(lrnet.init_params(99))
+    b.load_state(st)
+    la = float(a.step(feat, label).item())
+    lb = float(b.step(feat, label).item())
+    assert la == lb
+    assert np.array_equal(host(a.params), host(b.params))
