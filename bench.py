@@ -71,6 +71,42 @@ def cpu_baseline(fr, D):
             "seconds": dt}
 
 
+def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
+    """Learned frame (right views skipped, network mask): fps, speed-up over the
+    plain frame, and agreement of its masks with the plain LR check on this frame."""
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import lrnet
+    from paper_1801_04720_amd.pipeline import FusedFrame
+
+    trained = os.path.exists(args.lrnet)
+    if trained:
+        with np.load(args.lrnet, allow_pickle=False) as z:
+            prm = z["params"].astype(np.float32)
+    else:
+        prm = lrnet.init_params(0)
+    prm_t = torch.from_numpy(prm).to(dev)
+    lp = FusedFrame(H, W, D, learned_params=prm_t, device=dev)
+    for _ in range(args.warmup):
+        lp.run(*inputs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = lp.run(*inputs)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    plain = plain_pipe.run(*inputs)
+    torch.cuda.synchronize()
+    agree = [float((out[k] == plain[k]).float().mean().item()) for k in ("valid0", "valid1")]
+    both = lambda m: float((m & 1).float().mean().item())  # noqa: E731
+    return {"fps_learned": 1e3 / ms, "ms_learned": ms, "speedup_learned_vs_plain": ms_plain / ms,
+            "gcups_learned_delivered": 2 * H * W * D * 8 / (ms * 1e-3) / 1e9,
+            "learned_weights": os.path.relpath(args.lrnet, ROOT) if trained else "untrained init",
+            "lr_mask_agreement_t0_t1": agree,
+            "sceneflow_density_learned": both(out["valid"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +117,10 @@ def main():
                     help="fused: sf_frame_run; persistent: same with persistent aggregation "
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
+    ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
+                                                    "lrnet_c2.npz"),
+                    help="trained parameters of the learned LR stand-in (.npz)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference kernel "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -186,6 +226,8 @@ def main():
         "kernels": breakdown,
         "roofline": roofline,
     }
+    if not args.no_learned and args.pipeline != "stages":
+        res.update(learned_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)

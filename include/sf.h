@@ -166,11 +166,15 @@ int sf_plan_destroy(sf_plan plan);
  * WTA + sub-pixel + LR check (as sf_wta_lr, but summing the per-direction path
  * costs on the fly instead of materialising S), then sf_combine's
  * combination and triangulation with the given flow.
- *   persistent: 0 = one block per aggregation task; 1 = persistent blocks
- *               pulling tasks from a counter (same results).
+ *   flags: SF_FRAME_PERSISTENT = persistent aggregation blocks pulling tasks
+ *          from a counter (same results); SF_FRAME_LEARNED = the learned
+ *          frame (sf_frame_run_learned): the right-view aggregations are
+ *          skipped and the LR check is replaced by the network's mask.
  * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (device table upload). */
-int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int persistent,
+#define SF_FRAME_PERSISTENT 1
+#define SF_FRAME_LEARNED 2
+int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
                          sf_plan *plan);
 /* L0, R0, L1, R1 [H][pitch] uint8; flow [H][W][2]; cam host pointer or NULL.
  * Outputs: disp0/valid0 (t0 map), disp1/valid1 (t1 map), as sf_wta_lr;
@@ -181,6 +185,17 @@ int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8
                  float *disp0, uint8_t *valid0, float *disp1, uint8_t *valid1, float *sf4,
                  uint8_t *valid, float *xyz0, float *motion, void *workspace, size_t ws_bytes,
                  void *stream);
+
+/* Learned frame (plan created with SF_FRAME_LEARNED): as sf_frame_run, except
+ * that only the two left-base views are aggregated, WTA also writes the
+ * network's features, and each map's validity is sf_lrnet_mask of
+ * sf_lrnet_forward (lr_params: device FP32 parameters, see below) instead of
+ * the left-right check. */
+int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8_t *L1,
+                         const uint8_t *R1, int pitch, const float *flow, const sf_camera *cam,
+                         const float *lr_params, float *disp0, uint8_t *valid0, float *disp1,
+                         uint8_t *valid1, float *sf4, uint8_t *valid, float *xyz0, float *motion,
+                         void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Learned stand-in for the left-right check (the check is the paper's, Sec.

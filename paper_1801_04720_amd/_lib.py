@@ -54,6 +54,8 @@ SIGNATURES = {
     "sf_lrnet_mask": (I, [P, P, P, I, I, P, P, P]),
     "sf_lrnet_grad": (I, [P, P, P, I, I, I, P, P, P, SZ, P]),
     "sf_lrnet_adam": (I, [P, P, P, P, I, F, F, F, F, F, F, P]),
+    "sf_frame_run_learned": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P,
+                                 P, P, SZ, P]),
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),

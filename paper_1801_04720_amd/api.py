@@ -161,10 +161,14 @@ class Plan:
             pass
 
 
+FRAME_PERSISTENT, FRAME_LEARNED = 1, 2
+
+
 def frame_plan(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
-               persistent: bool = False) -> Plan:
+               persistent: bool = False, learned: bool = False) -> Plan:
     h = ct.c_void_p()
-    check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, int(persistent), ct.byref(h)))
+    flags = (FRAME_PERSISTENT if persistent else 0) | (FRAME_LEARNED if learned else 0)
+    check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, ct.byref(h)))
     return Plan(h)
 
 
@@ -176,4 +180,17 @@ def frame_run(plan: Plan, L0, R0, L1, R1, flow, cam, out: dict, workspace, strea
                              _ptr(out["disp1"]), _ptr(out["valid1"]), _ptr(out["sf4"]),
                              _ptr(out["valid"]), _ptr(out.get("xyz0")), _ptr(out.get("motion")),
                              _ptr(workspace), workspace.numel(), _stream(stream)))
+    return out
+
+
+def frame_run_learned(plan: Plan, L0, R0, L1, R1, flow, cam, params, out: dict, workspace,
+                      stream=None):
+    """Learned frame: right views skipped, validity from the network's mask."""
+    camp = ct.byref(SfCamera(*[float(c) for c in cam])) if cam is not None else None
+    check(lib().sf_frame_run_learned(plan.handle, _ptr(L0), _ptr(R0), _ptr(L1), _ptr(R1),
+                                     L0.stride(0), _ptr(flow), camp, _ptr(params),
+                                     _ptr(out["disp0"]), _ptr(out["valid0"]), _ptr(out["disp1"]),
+                                     _ptr(out["valid1"]), _ptr(out["sf4"]), _ptr(out["valid"]),
+                                     _ptr(out.get("xyz0")), _ptr(out.get("motion")),
+                                     _ptr(workspace), workspace.numel(), _stream(stream)))
     return out

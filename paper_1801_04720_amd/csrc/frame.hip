@@ -48,7 +48,7 @@ int default_persistent_blocks()
 
 using namespace sf;
 
-extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int persistent,
+extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
                                     sf_plan *out)
 {
     clear_error();
@@ -63,27 +63,39 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_frame_plan_create: lr_tol < 0");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED,
                "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
+    SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED)) == 0, SF_EINVAL,
+               "sf_frame_plan_create: unknown flags");
     Plan *p = new (std::nothrow) Plan();
     if (!p) return fail(SF_ENOMEM, "sf_frame_plan_create: out of host memory");
     p->kind = Plan::FRAME;
+    p->learned = (flags & SF_FRAME_LEARNED) != 0;
     p->H = H;
     p->W = W;
     p->D = D;
     p->P1 = P1;
     p->P2 = P2;
     p->tol = lr_tol;
+    // Views aggregated: plain = L0, R0, L1, R1 bases; learned = L0, L1 bases only.
+    const int nv = p->learned ? 2 : 4;
     const size_t npx = (size_t)H * W, ncell = npx * D;
     size_t off = 0;
     for (int i = 0; i < 4; ++i) { p->off_cen[i] = off; off += align256(npx * 8); }
-    for (int i = 0; i < 4; ++i) { p->off_cost[i] = off; off += align256(ncell); }
-    for (int i = 0; i < 4; ++i) { p->off_slab[i] = off; off += align256(8 * ncell); }
+    for (int i = 0; i < nv; ++i) { p->off_cost[i] = off; off += align256(ncell); }
+    for (int i = 0; i < nv; ++i) { p->off_slab[i] = off; off += align256(8 * ncell); }
     for (int i = 0; i < 2; ++i) { p->off_wtar[i] = off; off += align256(npx * 2); }
     for (int i = 0; i < 2; ++i) { p->off_wtal[i] = off; off += align256(npx * 2); }
+    if (p->learned) {
+        p->off_feat = off; off += align256(2 * npx * 16);
+        for (int i = 0; i < 2; ++i) { p->off_dsub[i] = off; off += align256(npx * 4); }
+        for (int i = 0; i < 2; ++i) { p->off_vtmp[i] = off; off += align256(npx); }
+        p->off_logit = off; off += align256(2 * npx * 4);
+        p->off_lrws = off; off += align256(lrnet_forward_ws_bytes(2, H, W));
+    }
     p->ws_bytes = off;
-    std::vector<AggView> views(4);
+    std::vector<AggView> views(nv);
     std::vector<AggTask> tasks;
     std::vector<int> lens;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < nv; ++i) {
         AggView &v = views[i];
         v.cost_off = p->off_cost[i];
         v.slab_off = p->off_slab[i];
@@ -102,7 +114,7 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
         sf_plan_destroy(reinterpret_cast<sf_plan>(p));
         return rc;
     }
-    p->persistent_blocks = persistent ? default_persistent_blocks() : 0;
+    p->persistent_blocks = (flags & SF_FRAME_PERSISTENT) ? default_persistent_blocks() : 0;
     *out = reinterpret_cast<sf_plan>(p);
     return SF_OK;
 }
@@ -130,7 +142,8 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     clear_error();
     SF_REQUIRE(plan, SF_EINVAL, "sf_frame_run: NULL plan");
     Plan *p = reinterpret_cast<Plan *>(plan);
-    SF_REQUIRE(p->kind == Plan::FRAME, SF_EINVAL, "sf_frame_run: not a frame plan");
+    SF_REQUIRE(p->kind == Plan::FRAME && !p->learned, SF_EINVAL,
+               "sf_frame_run: not a plain frame plan");
     SF_REQUIRE(L0 && R0 && L1 && R1 && flow && disp0 && valid0 && disp1 && valid1 && sf4 && valid,
                SF_EINVAL, "sf_frame_run: NULL pointer");
     SF_REQUIRE(pitch >= p->W, SF_EINVAL, "sf_frame_run: pitch < W");
@@ -199,5 +212,81 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     rc = launch_wta_slabs(wl, st);
     if (rc) return rc;
 
+    return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
+}
+
+extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0,
+                                    const uint8_t *L1, const uint8_t *R1, int pitch,
+                                    const float *flow, const sf_camera *cam, const float *lr_params,
+                                    float *disp0, uint8_t *valid0, float *disp1, uint8_t *valid1,
+                                    float *sf4, uint8_t *valid, float *xyz0, float *motion,
+                                    void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(plan, SF_EINVAL, "sf_frame_run_learned: NULL plan");
+    Plan *p = reinterpret_cast<Plan *>(plan);
+    SF_REQUIRE(p->kind == Plan::FRAME && p->learned, SF_EINVAL,
+               "sf_frame_run_learned: not a learned frame plan");
+    SF_REQUIRE(L0 && R0 && L1 && R1 && flow && lr_params && disp0 && valid0 && disp1 && valid1 &&
+                   sf4 && valid,
+               SF_EINVAL, "sf_frame_run_learned: NULL pointer");
+    SF_REQUIRE(pitch >= p->W, SF_EINVAL, "sf_frame_run_learned: pitch < W");
+    SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL,
+               "sf_frame_run_learned: camera given without xyz0/motion");
+    if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_frame_run_learned: focal length is zero");
+    SF_REQUIRE(workspace, SF_EINVAL, "sf_frame_run_learned: NULL workspace");
+    SF_REQUIRE(ws_bytes >= p->ws_bytes, SF_ENOMEM, "sf_frame_run_learned: workspace too small");
+    hipStream_t st = as_stream(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    const int H = p->H, W = p->W, D = p->D;
+    auto at = [&](size_t off) { return ws + off; };
+    const uint8_t *img[4] = {L0, R0, L1, R1};
+    uint64_t *cen[4];
+    for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
+    CensusArgs ca{};
+    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; }
+    ca.n = 4; ca.H = H; ca.W = W; ca.pitch = pitch;
+    int rc = launch_census(ca, st);
+    if (rc) return rc;
+    // Left-base cost volumes only: views 0 = L0 base, 1 = L1 base.
+    CostArgs co{};
+    for (int t = 0; t < 2; ++t) {
+        co.base[t] = cen[2 * t];
+        co.match[t] = cen[2 * t + 1];
+        co.right[t] = 0;
+        co.cost[t] = at(p->off_cost[t]);
+    }
+    co.n = 2; co.H = H; co.W = W; co.D = D;
+    if ((rc = launch_cost(co, st))) return rc;
+    if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
+                               p->persistent_blocks, st)))
+        return rc;
+    // WTA + sub-pixel + features of both left maps (no right view).
+    float *feat = reinterpret_cast<float *>(at(p->off_feat));
+    WtaArgs wl{};
+    for (int t = 0; t < 2; ++t) {
+        WtaView &v = wl.v[t];
+        v.slab = at(p->off_slab[t]);
+        v.wta_r = nullptr;
+        v.img = img[2 * t];
+        v.pitch = pitch;
+        v.wta = reinterpret_cast<int16_t *>(at(p->off_wtal[t]));
+        v.disp = reinterpret_cast<float *>(at(p->off_dsub[t]));
+        v.valid = at(p->off_vtmp[t]);
+        v.feat = feat + (size_t)t * H * W * 4;
+        v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 0;
+    }
+    wl.n = 2;
+    if ((rc = launch_wta_slabs(wl, st))) return rc;
+    float *logits = reinterpret_cast<float *>(at(p->off_logit));
+    if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st))) return rc;
+    float *dsp[2] = {disp0, disp1};
+    uint8_t *vld[2] = {valid0, valid1};
+    for (int t = 0; t < 2; ++t)
+        if ((rc = launch_lr_mask(logits + (size_t)t * H * W,
+                                 reinterpret_cast<const int16_t *>(at(p->off_wtal[t])),
+                                 reinterpret_cast<const float *>(at(p->off_dsub[t])), H, W, vld[t],
+                                 dsp[t], st)))
+            return rc;
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
 }

@@ -22,6 +22,7 @@
 //              (K = pixels), per-block partials reduced in a fixed order
 //   adam       FP32 Adam step.
 #include "sf_internal.hpp"
+#include "stages.hpp"
 
 namespace sf {
 
@@ -497,6 +498,8 @@ static LrLayout lr_layout(int B, int H, int W, bool train)
     return L;
 }
 
+size_t lrnet_forward_ws_bytes(int B, int H, int W) { return lr_layout(B, H, W, false).total; }
+
 }  // namespace sf
 
 using namespace sf;
@@ -549,6 +552,25 @@ static int lr_forward(const float *params, const float *feat, int B, int H, int 
     return launch_status("lrnet forward");
 }
 
+namespace sf {
+int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
+                  uint8_t *ws, hipStream_t st)
+{
+    return lr_forward(params, feat, B, H, W, ws, lr_layout(B, H, W, false), logits, nullptr, nullptr,
+                      nullptr, st);
+}
+
+int launch_lr_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
+                   uint8_t *valid, float *disp, hipStream_t st)
+{
+    const int n = H * W;
+    ProfScope prof("lrnet_mask", st);
+    hipLaunchKernelGGL(lr_mask_kernel, dim3((n + 255) / 256), dim3(256), 0, st, logits, wta, dsub, H,
+                       W, valid, disp);
+    return launch_status("lr_mask_kernel");
+}
+}  // namespace sf
+
 extern "C" int sf_lrnet_forward(const float *params, const float *feat, int B, int H, int W,
                                 float *logits, void *workspace, size_t ws_bytes, void *stream)
 {
@@ -567,11 +589,7 @@ extern "C" int sf_lrnet_mask(const float *logits, const int16_t *wta, const floa
     clear_error();
     SF_REQUIRE(logits && wta && dsub && valid && disp, SF_EINVAL, "sf_lrnet_mask: NULL pointer");
     SF_REQUIRE(H > 0 && W > 0 && (long long)H * W <= (1LL << 30), SF_EINVAL, "sf_lrnet_mask: bad size");
-    const int n = H * W;
-    ProfScope prof("lrnet_mask", as_stream(stream));
-    hipLaunchKernelGGL(lr_mask_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), logits,
-                       wta, dsub, H, W, valid, disp);
-    return launch_status("lr_mask_kernel");
+    return launch_lr_mask(logits, wta, dsub, H, W, valid, disp, as_stream(stream));
 }
 
 extern "C" int sf_lrnet_grad(const float *params, const float *feat, const uint8_t *label, int B,

@@ -49,6 +49,11 @@ struct WtaArgs {
 int launch_census(const CensusArgs &a, hipStream_t st);
 int launch_cost(const CostArgs &a, hipStream_t st);
 int launch_wta_slabs(WtaArgs &a, hipStream_t st);  // fills blk0
+size_t lrnet_forward_ws_bytes(int B, int H, int W);
+int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
+                  uint8_t *ws, hipStream_t st);
+int launch_lr_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
+                   uint8_t *valid, float *disp, hipStream_t st);
 int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
                    const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
                    float *sf4, uint8_t *valid, float *xyz0, float *motion, hipStream_t st);

@@ -57,11 +57,14 @@ class FusedFrame:
     all four aggregations in one launch, S never materialised."""
 
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
-                 cam=(721.5, 0.54, None, None), persistent: bool = False, device="cuda:0"):
+                 cam=(721.5, 0.54, None, None), persistent: bool = False, learned_params=None,
+                 device="cuda:0"):
         self.H, self.W, self.D = H, W, D
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
-        self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent)
+        self.params = learned_params
+        self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent,
+                                   learned=learned_params is not None)
         dev = torch.device(device)
         e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
         self.ws = e(self.plan.workspace_bytes(), dt=torch.uint8)
@@ -71,4 +74,7 @@ class FusedFrame:
                     "xyz0": e(H, W, 3, dt=torch.float32), "motion": e(H, W, 3, dt=torch.float32)}
 
     def run(self, L0, R0, L1, R1, flow):
+        if self.params is not None:
+            return api.frame_run_learned(self.plan, L0, R0, L1, R1, flow, self.cam, self.params,
+                                         self.out, self.ws)
         return api.frame_run(self.plan, L0, R0, L1, R1, flow, self.cam, self.out, self.ws)

@@ -90,3 +90,37 @@ def test_fused_frame_repeatable():
     b = {k: host(v).copy() for k, v in ff.run(*args).items()}
     for k in a:
         assert np.array_equal(a[k], b[k], equal_nan=True), k
+
+
+def test_learned_frame_equals_stagewise(orc):
+    """Learned frame == its stages called one by one through the C ABI (each stage is
+    pinned against the oracle in its own tests); the plain left maps agree with the
+    oracle's WTA, and the learned masks never keep a pixel with x - d* < 0."""
+    from paper_1801_04720_amd import api, lrnet
+
+    say("learned frame vs stage-by-stage")
+    H, W, D = 64, 200, 64
+    fr = synth.frame_planar(synth.rng_for(8, 11), H, W, D, 25.0)
+    prm = dev(lrnet.init_params(5))
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    ff = FusedFrame(H, W, D, learned_params=prm, device=DEV)
+    got = {k: host(v).copy() for k, v in ff.run(*args).items()}
+    maps = []
+    for t in range(2):
+        L, R = args[2 * t], args[2 * t + 1]
+        cl, cr = api.census(L), api.census(R)
+        Sl = api.sgm_aggregate(api.cost(cl, cr, D, False), 10, 120)
+        m = api.wta_lr(Sl, None, L, 120, 1, want_feat=True)
+        logits = lrnet.forward(prm, m["feat"][None].contiguous())
+        valid, disp = lrnet.mask(logits[0], m["wta_left"], m["disp"])
+        maps.append((valid, disp, m["wta_left"]))
+    c = api.combine(maps[0][1], maps[0][0], maps[1][1], maps[1][0], args[4], ff.cam)
+    torch.cuda.synchronize()
+    assert np.array_equal(got["valid0"], host(maps[0][0]))
+    assert np.array_equal(got["disp1"], host(maps[1][1]))
+    for k in ("sf4", "valid", "xyz0", "motion"):
+        assert np.array_equal(got[k], host(c[k]), equal_nan=True), k
+    w0, _ = orc.wta(orc.aggregate(orc.cost(orc.census(fr.t0.left), orc.census(fr.t0.right), D, False), 10, 120))
+    assert np.array_equal(host(maps[0][2]), w0)
+    xs = np.arange(W)[None, :]
+    assert not (got["valid0"].astype(bool) & ((xs - w0) < 0)).any()
