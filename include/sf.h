@@ -198,6 +198,53 @@ int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, con
                          void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched plain SGM: many stereo pairs of uneven size and disparity range, each
+ * processed exactly as a plain pair (census, both cost volumes, 8-path
+ * aggregation of both views, WTA + sub-pixel + LR check; same results as
+ * sf_census .. sf_wta_lr on that pair alone).  The plan groups pairs by size
+ * class and packs them into waves whose workspace fits mem_budget bytes (0 =
+ * one wave); each wave runs one aggregation launch per size class from a
+ * device task table.  Device pointers in the pair descriptors are fixed at plan
+ * creation and must stay valid while the plan is used.
+ * Tuning of the aggregation per size class (classes numbered in order of first
+ * appearance in `pairs`; NULL / missing = {16, 8, 0, 0}):
+ *   chains_per_block  4, 8 or 16 chains (16-lane rows) per block
+ *   prefetch          4 or 8 cost steps in flight per chain
+ *   order             0 = tasks longest chains first, 1 = view by view
+ *   persistent_per_cu 0 = one block per task; k > 0 = k blocks per CU pulling
+ *                     tasks from a counter
+ * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255.
+ * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (table upload). */
+typedef struct {
+    int H, W, D, pitch;
+    const uint8_t *left, *right; /* [H][pitch] */
+    int16_t *wta;                /* [H][W] d*_L or NULL */
+    float *disp;                 /* [H][W] d_sub or -1 */
+    uint8_t *valid;              /* [H][W] LR-check mask */
+} sf_pair;
+
+typedef struct {
+    int chains_per_block, prefetch, order, persistent_per_cu;
+} sf_agg_tuning;
+
+int sf_batch_plan_create(const sf_pair *pairs /* host array */, int n, int P1, int P2, int lr_tol,
+                         const sf_agg_tuning *tunings /* host, per class */, int ntunings,
+                         size_t mem_budget, sf_plan *plan);
+int sf_batch_plan_info(sf_plan plan, int *nwaves, int *nclasses);
+/* Enqueue the whole batch on stream (eager). */
+int sf_batch_run(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
+/* Capture the whole batch on a non-default stream into a HIP graph owned by the
+ * plan (the workspace address is baked in), then replay it with one call. */
+int sf_batch_capture(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
+int sf_batch_launch(sf_plan plan, void *stream);
+/* Autotuner: times every candidate tuning (chains per block x prefetch x order x
+ * persistence) of the aggregation of one H x W x D pair (both views, synthetic
+ * costs) on `stream`, and returns the fastest and its median time.  Allocates
+ * and frees its own scratch; synchronises the stream. */
+int sf_agg_autotune(int H, int W, int D, int P1, int P2, void *stream, sf_agg_tuning *best,
+                    float *best_ms);
+
+/* ---------------------------------------------------------------------------
  * Learned stand-in for the left-right check (the check is the paper's, Sec.
  * 3.1; the network is not: it predicts from the left view alone which pixels
  * the check would keep, so the right-view aggregation can be skipped).

@@ -26,6 +26,17 @@ class SfCamera(ct.Structure):
     _fields_ = [("f", ct.c_float), ("B", ct.c_float), ("cx", ct.c_float), ("cy", ct.c_float)]
 
 
+class SfPair(ct.Structure):
+    _fields_ = [("H", ct.c_int), ("W", ct.c_int), ("D", ct.c_int), ("pitch", ct.c_int),
+                ("left", ct.c_void_p), ("right", ct.c_void_p), ("wta", ct.c_void_p),
+                ("disp", ct.c_void_p), ("valid", ct.c_void_p)]
+
+
+class SfAggTuning(ct.Structure):
+    _fields_ = [("chains_per_block", ct.c_int), ("prefetch", ct.c_int), ("order", ct.c_int),
+                ("persistent_per_cu", ct.c_int)]
+
+
 class SfError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
@@ -56,6 +67,13 @@ SIGNATURES = {
     "sf_lrnet_adam": (I, [P, P, P, P, I, F, F, F, F, F, F, P]),
     "sf_frame_run_learned": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P,
                                  P, P, SZ, P]),
+    "sf_batch_plan_create": (I, [ct.POINTER(SfPair), I, I, I, I, ct.POINTER(SfAggTuning), I, SZ,
+                                 ct.POINTER(P)]),
+    "sf_batch_plan_info": (I, [P, ct.POINTER(I), ct.POINTER(I)]),
+    "sf_batch_run": (I, [P, P, SZ, P]),
+    "sf_batch_capture": (I, [P, P, SZ, P]),
+    "sf_batch_launch": (I, [P, P]),
+    "sf_agg_autotune": (I, [I, I, I, I, I, P, ct.POINTER(SfAggTuning), ct.POINTER(F)]),
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),

@@ -15,7 +15,7 @@ constexpr int CEN_RY = 3;   // window half-height (7 tall)
 // in LDS with clamp-to-edge, coalesced along rows.
 __global__ __launch_bounds__(CEN_TW *CEN_TH) void census_kernel(CensusArgs a)
 {
-    const int H = a.H, W = a.W, pitch = a.pitch;
+    const int H = a.H, W = a.W, pitch = a.pitch[blockIdx.z];
     const uint8_t *__restrict__ img = a.img[blockIdx.z];
     uint64_t *__restrict__ out = a.out[blockIdx.z];
     constexpr int LW = CEN_TW + 2 * CEN_RX;
@@ -142,10 +142,10 @@ extern "C" int sf_census(const uint8_t *img, int H, int W, int pitch, uint64_t *
     CensusArgs a{};
     a.img[0] = img;
     a.out[0] = census;
+    a.pitch[0] = pitch;
     a.n = 1;
     a.H = H;
     a.W = W;
-    a.pitch = pitch;
     return launch_census(a, as_stream(stream));
 }
 

@@ -129,6 +129,7 @@ extern "C" int sf_plan_destroy(sf_plan plan)
     if (!plan) return SF_OK;
     Plan *p = reinterpret_cast<Plan *>(plan);
     if (p->d_tables) hipFree(p->d_tables);
+    if (p->batch) destroy_batch(p->batch);
     delete p;
     return SF_OK;
 }
@@ -160,8 +161,8 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
 
     CensusArgs ca{};
-    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; }
-    ca.n = 4; ca.H = H; ca.W = W; ca.pitch = pitch;
+    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; ca.pitch[i] = pitch; }
+    ca.n = 4; ca.H = H; ca.W = W;
     int rc = launch_census(ca, st);
     if (rc) return rc;
 
@@ -244,8 +245,8 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     uint64_t *cen[4];
     for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
     CensusArgs ca{};
-    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; }
-    ca.n = 4; ca.H = H; ca.W = W; ca.pitch = pitch;
+    for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; ca.pitch[i] = pitch; }
+    ca.n = 4; ca.H = H; ca.W = W;
     int rc = launch_census(ca, st);
     if (rc) return rc;
     // Left-base cost volumes only: views 0 = L0 base, 1 = L1 base.

@@ -10,6 +10,9 @@
 
 namespace sf {
 
+struct BatchData;
+void destroy_batch(BatchData *b);
+
 struct Plan {
     enum Kind { FRAME, BATCH, LRNET } kind = FRAME;
     int H = 0, W = 0, D = 0, P1 = 0, P2 = 0, tol = 0;
@@ -26,6 +29,8 @@ struct Plan {
     int *d_counter = nullptr;
     int ntasks = 0, nviews = 0;
     int persistent_blocks = 0;
+    // Batch plans: pairs, waves, per-class tunings, captured graph.
+    BatchData *batch = nullptr;
 };
 
 int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::vector<AggTask> &tasks);

@@ -161,13 +161,13 @@ __device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_p
     }
 }
 
-// Prefetch depth (steps) of the cost stream of one chain.
+// Default prefetch depth (steps) of the cost stream of one chain.
 constexpr int SGM_U = 8;
 
 // Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
 // cost: [H][W][D]; slab: this direction's [H][W][D] u8 slab (ATOMIC == false)
 // or S [H][W][D] u16 (ATOMIC == true).
-template <int K, bool ATOMIC>
+template <int K, bool ATOMIC, int U = SGM_U>
 __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
                                           uint16_t *__restrict__ S, int H, int W, int P1, int P2,
                                           int r, int l, int j)
@@ -191,9 +191,9 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     // for row_shr, lane 15 for row_shl) keep the "no neighbour" value forever.
     uint32_t below = SGM_SENT, above = SGM_SENT;
 
-    auto fetch = [&](int t0, CostRaw<K>(&buf)[SGM_U]) {
+    auto fetch = [&](int t0, CostRaw<K>(&buf)[U]) {
 #pragma unroll
-        for (int u = 0; u < SGM_U; ++u) {
+        for (int u = 0; u < U; ++u) {
             if (t0 + u < len) load_raw<K>(ld, buf[u]);
             ld += bstep;
         }
@@ -237,15 +237,15 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
         M = row16_min(min((uint32_t)m2.x, (uint32_t)m2.y));
     };
 
-    CostRaw<K> bufA[SGM_U], bufB[SGM_U];
+    CostRaw<K> bufA[U], bufB[U];
     fetch(0, bufA);
-    for (int t0 = 0; t0 < len; t0 += 2 * SGM_U) {
-        fetch(t0 + SGM_U, bufB);
+    for (int t0 = 0; t0 < len; t0 += 2 * U) {
+        fetch(t0 + U, bufB);
 #pragma unroll
-        for (int u = 0; u < SGM_U; ++u) step(t0 + u, bufA[u]);
-        fetch(t0 + 2 * SGM_U, bufA);
+        for (int u = 0; u < U; ++u) step(t0 + u, bufA[u]);
+        fetch(t0 + 2 * U, bufA);
 #pragma unroll
-        for (int u = 0; u < SGM_U; ++u) step(t0 + SGM_U + u, bufB[u]);
+        for (int u = 0; u < U; ++u) step(t0 + U + u, bufB[u]);
     }
 }
 
@@ -268,9 +268,10 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
 }
 
 // Many views from a task table (all tasks of one launch share K = D / 16).
-// persistent: gridDim.x blocks pull task indices from *counter (zeroed before
-// the launch) until the table is done; otherwise block b runs task b.
-template <int K>
+// A block of 16 * c threads runs one task of up to c chains.  persistent:
+// gridDim.x blocks pull task indices from *counter (zeroed before the launch)
+// until the table is done; otherwise block b runs task b.
+template <int K, int U>
 __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
                                                            const AggTask *__restrict__ tasks,
                                                            int ntasks, uint8_t *base,
@@ -293,8 +294,8 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
             const uint8_t *cost = reinterpret_cast<const uint8_t *>((uintptr_t)base + v.cost_off);
             uint8_t *slab = reinterpret_cast<uint8_t *>((uintptr_t)base + v.slab_off) +
                             (size_t)tk.slot * v.H * v.W * (16 * K);
-            sgm_chain<K, false>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
-                                tk.line0 + q, j);
+            sgm_chain<K, false, U>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
+                                   tk.line0 + q, j);
         }
         if (!counter) return;
     }
@@ -377,13 +378,13 @@ static int chain_len(int r, int l, int H, int W)
 }
 
 void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, int view,
-                      const AggView &v)
+                      const AggView &v, int chains_per_task)
 {
     for (int s = 0; s < v.ndir; ++s) {
         const int r = v.dir[s];
         const int n = chains_of(r, v.H, v.W);
-        for (int l0 = 0; l0 < n; l0 += SGM_CPB) {
-            AggTask t{view, s, l0, n - l0 < SGM_CPB ? n - l0 : SGM_CPB};
+        for (int l0 = 0; l0 < n; l0 += chains_per_task) {
+            AggTask t{view, s, l0, n - l0 < chains_per_task ? n - l0 : chains_per_task};
             int mx = 0;
             for (int l = l0; l < l0 + t.nlines; ++l) mx = std::max(mx, chain_len(r, l, v.H, v.W));
             tasks.push_back(t);
@@ -403,16 +404,23 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
 }
 
 template <int K>
-static void launch_tasks_k(int nb, hipStream_t st, const AggView *v, const AggTask *t, int n,
-                           uint8_t *base, int *counter)
+static void launch_tasks_k(int U, int nb, int nthr, hipStream_t st, const AggView *v,
+                           const AggTask *t, int n, uint8_t *base, int *counter)
 {
-    hipLaunchKernelGGL((sgm_tasks_kernel<K>), dim3(nb), dim3(SGM_NT), 0, st, v, t, n, base, counter);
+    if (U == 4)
+        hipLaunchKernelGGL((sgm_tasks_kernel<K, 4>), dim3(nb), dim3(nthr), 0, st, v, t, n, base, counter);
+    else
+        hipLaunchKernelGGL((sgm_tasks_kernel<K, 8>), dim3(nb), dim3(nthr), 0, st, v, t, n, base, counter);
 }
 
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
-                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st)
+                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
+                     int chains_per_block, int prefetch)
 {
     if (ntasks <= 0) return SF_OK;
+    if (chains_per_block != 4 && chains_per_block != 8 && chains_per_block != 16)
+        return fail(SF_EINVAL, "launch_agg_tasks: chains per block must be 4, 8 or 16");
+    if (prefetch != 4 && prefetch != 8) return fail(SF_EINVAL, "launch_agg_tasks: prefetch must be 4 or 8");
     ProfScope prof("sgm_tasks", st);
     int nb = ntasks;
     int *counter = nullptr;
@@ -422,15 +430,16 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
         nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
         counter = d_counter;
     }
+    const int nthr = 16 * chains_per_block;
     switch (K) {
-    case 2: launch_tasks_k<2>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 4: launch_tasks_k<4>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 6: launch_tasks_k<6>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 8: launch_tasks_k<8>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 10: launch_tasks_k<10>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 12: launch_tasks_k<12>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 14: launch_tasks_k<14>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 16: launch_tasks_k<16>(nb, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 4: launch_tasks_k<4>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 6: launch_tasks_k<6>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 8: launch_tasks_k<8>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 10: launch_tasks_k<10>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 12: launch_tasks_k<12>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 14: launch_tasks_k<14>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
     default: return fail(SF_EUNSUPPORTED, "launch_agg_tasks: unsupported K");
     }
     return launch_status("sgm_tasks_kernel");

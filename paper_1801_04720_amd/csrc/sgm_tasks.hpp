@@ -28,11 +28,14 @@ struct AggTask {
 
 int chains_of(int r, int H, int W);
 void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, int view,
-                      const AggView &v);
+                      const AggView &v, int chains_per_task = 16);
 void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int> &task_len);
 // persistent_blocks > 0: persistent launch with that many blocks pulling from
 // *d_counter (reset on the stream first); 0: one block per task.
+// chains_per_block in {4, 8, 16} must match the table's chains per task;
+// prefetch (cost steps in flight per chain) in {4, 8}.
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
-                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st);
+                     uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
+                     int chains_per_block = 16, int prefetch = 8);
 
 }  // namespace sf

@@ -15,7 +15,8 @@ constexpr int STAGE_MAXV = 8;  // views per launch
 struct CensusArgs {
     const uint8_t *img[STAGE_MAXV];
     uint64_t *out[STAGE_MAXV];
-    int n, H, W, pitch;
+    int pitch[STAGE_MAXV];
+    int n, H, W;
 };
 
 struct CostArgs {

@@ -1,0 +1,122 @@
+"""Batched plain SGM over uneven pairs: every pair equals the oracle (small
+sizes) or the per-pair C-ABI path (larger ones) bit for bit, whatever the
+waves, tunings and schedule; the captured graph replays identically; the
+autotuner returns a valid choice."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1801_04720_amd import api, batch, synth  # noqa: E402
+from paper_1801_04720_amd._lib import SfAggTuning  # noqa: E402
+
+from gpu_util import DEV, assert_close_rel, dev, host  # noqa: E402
+
+SIZES = [(48, 160, 32), (61, 203, 64), (40, 97, 96), (33, 300, 256), (48, 160, 32), (61, 203, 64)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_pairs(sizes, cfg=7):
+    pairs, host_pairs = [], []
+    for i, (H, W, D) in enumerate(sizes):
+        p = synth.pair_planar(synth.rng_for(cfg, i), H, W, D)
+        host_pairs.append(p)
+        pairs.append({"left": dev(p.left), "right": dev(p.right), "D": D})
+    return pairs, host_pairs
+
+
+def per_pair_gpu(p):
+    L, R, D = p["left"], p["right"], p["D"]
+    cl, cr = api.census(L), api.census(R)
+    Sr = api.sgm_aggregate(api.cost(cr, cl, D, True), 10, 120)
+    Sl = api.sgm_aggregate(api.cost(cl, cr, D, False), 10, 120)
+    return api.wta_lr(Sl, Sr, None, 120, 1)
+
+
+def test_batch_vs_oracle(orc):
+    say("batch vs oracle")
+    pairs, hp = make_pairs(SIZES)
+    b = batch.Batch(pairs)
+    out = b.run()
+    torch.cuda.synchronize()
+    for o, p in zip(out, hp):
+        w, d, v = orc.disparity(p.left, p.right, p.D)
+        assert np.array_equal(host(o["wta"]), w)
+        assert np.array_equal(host(o["valid"]), v)
+        assert_close_rel(host(o["disp"]), d, 1.0)
+
+
+@pytest.mark.parametrize("cpb,pf,order,pers", [(4, 4, 0, 0), (8, 8, 1, 0), (16, 4, 1, 4), (4, 8, 0, 8),
+                                               (16, 8, 0, 2)])
+def test_batch_tunings_and_waves_identical(cpb, pf, order, pers):
+    say("batch tuning", cpb, pf, order, pers)
+    pairs, _ = make_pairs(SIZES)
+    ref = [{k: host(v).copy() for k, v in o.items()} for o in batch.Batch(pairs).run()]
+    t = SfAggTuning(cpb, pf, order, pers)
+    b = batch.Batch(pairs, tunings=[t] * 4, mem_budget=8 << 20)  # tiny budget: several waves
+    assert b.nwaves > 1
+    out = b.run()
+    torch.cuda.synchronize()
+    for o, r in zip(out, ref):
+        for k in r:
+            assert np.array_equal(host(o[k]), r[k]), k
+
+
+def test_graph_replays_match_eager():
+    say("batch graph")
+    pairs, _ = make_pairs(SIZES[:4], cfg=8)
+    b = batch.Batch(pairs)
+    eager = [{k: host(v).copy() for k, v in o.items()} for o in b.run()]
+    s = torch.cuda.Stream()
+    b.capture(s)
+    for rep in range(3):
+        for o in b.out:  # scribble over the outputs between replays
+            for v in o.values():
+                v.fill_(7)
+        torch.cuda.synchronize()
+        b.launch(s)
+        s.synchronize()
+        x = torch.ones(1000, device=DEV).sum()  # unrelated eager work in between
+        torch.cuda.synchronize()
+        assert float(x) == 1000.0
+        for o, r in zip(b.out, eager):
+            for k in r:
+                assert np.array_equal(host(o[k]), r[k]), (rep, k)
+
+
+def test_batch_c3_classes_vs_per_pair_path():
+    """The three size classes of the uneven batch (640x480/64, 1242x375/128,
+    1920x1080/256), two pairs each, against the per-pair C-ABI path."""
+    say("batch c3 classes")
+    sizes = [(480, 640, 64), (375, 1242, 128), (1080, 1920, 256)] * 2
+    pairs, _ = make_pairs(sizes, cfg=3)
+    b = batch.Batch(pairs, mem_budget=16 << 30)
+    out = b.run()
+    torch.cuda.synchronize()
+    for o, p in zip(out, pairs):
+        r = per_pair_gpu(p)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(o["wta"]), host(r["wta_left"]))
+        assert np.array_equal(host(o["valid"]), host(r["valid"]))
+        assert np.array_equal(host(o["disp"]), host(r["disp"]))
+
+
+def test_autotune_returns_valid_choice(tmp_path):
+    say("autotune")
+    t, ms = batch.autotune(96, 320, 32, cache=str(tmp_path / "at.json"))
+    assert t.chains_per_block in (4, 8, 16) and t.prefetch in (4, 8)
+    assert t.order in (0, 1) and 0 <= t.persistent_per_cu <= 8
+    assert ms > 0
+    t2, ms2 = batch.autotune(96, 320, 32, cache=str(tmp_path / "at.json"))
+    assert (t2.chains_per_block, t2.prefetch, t2.order, t2.persistent_per_cu) == \
+        (t.chains_per_block, t.prefetch, t.order, t.persistent_per_cu)
