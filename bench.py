@@ -71,6 +71,119 @@ def cpu_baseline(fr, D):
             "seconds": dt}
 
 
+def _gen_pair(arg):
+    from paper_1801_04720_amd import synth
+
+    i, (H, W, D) = arg
+    p = synth.pair_batch(i, H, W, D)
+    return p.left, p.right
+
+
+def bench_batch(args, dev):
+    """Uneven batch: one captured graph for all pairs, per-class GCUPS, and the
+    speed-up over running the same pairs one by one through the C-ABI stages."""
+    import concurrent.futures as cf
+
+    import torch
+
+    from paper_1801_04720_amd import api, batch, synth
+
+    sizes = synth.batch_sizes(args.pairs)
+    with cf.ProcessPoolExecutor(max_workers=12) as ex:
+        imgs = list(ex.map(_gen_pair, list(enumerate(sizes)), chunksize=2))
+    pairs = [{"left": torch.from_numpy(L).to(dev), "right": torch.from_numpy(R).to(dev), "D": D}
+             for (L, R), (_, _, D) in zip(imgs, sizes)]
+    classes = []
+    for s_ in sizes:
+        if s_ not in classes:
+            classes.append(s_)
+    tunings, tune_info = {}, {}
+    for (H, W, D) in classes:
+        t, ms = batch.autotune(H, W, D, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+        tunings[(H, W, D)] = t
+        tune_info[f"{W}x{H}xD{D}"] = dict(batch.tuning_dict(t), aggregation_ms_per_pair=ms)
+    budget = int(args.mem_budget_gb * (1 << 30))
+
+    def time_graph(prs, steps, warmup):
+        b = batch.Batch(prs, tunings=tunings, mem_budget=budget, device=dev)
+        s = torch.cuda.Stream()
+        b.capture(s)
+        for _ in range(warmup):
+            b.launch(s)
+        s.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(steps):
+            b.launch(s)
+        e1.record(s)
+        s.synchronize()
+        return e0.elapsed_time(e1) / steps, b
+
+    steps = max(1, min(args.steps, 10))
+    ms_batch, b = time_graph(pairs, steps, max(1, args.warmup))
+    cells = lambda prs: sum(p["left"].shape[0] * p["left"].shape[1] * p["D"] * 8 for p in prs)  # noqa: E731
+    per_class = {}
+    for (H, W, D) in classes:
+        prs = [p for p in pairs if (p["left"].shape[0], p["left"].shape[1], p["D"]) == (H, W, D)]
+        ms_c, _ = time_graph(prs, steps, 1)
+        per_class[f"{W}x{H}xD{D}"] = {"pairs": len(prs), "ms": ms_c,
+                                     "gcups_delivered": cells(prs) / (ms_c * 1e-3) / 1e9,
+                                     "gcups_all_passes": 2 * cells(prs) / (ms_c * 1e-3) / 1e9}
+    # Plain form: the same pairs one by one through the per-stage C-ABI calls.
+    bufs = {}
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def plain_pair(p):
+        H, W = p["left"].shape
+        D = p["D"]
+        k = (H, W, D)
+        if k not in bufs:
+            bufs[k] = {"cost": torch.empty((H, W, D), dtype=torch.uint8, device=dev),
+                       "Sl": torch.empty((H, W, D), dtype=torch.int16, device=dev),
+                       "Sr": torch.empty((H, W, D), dtype=torch.int16, device=dev),
+                       "ws": torch.empty(api.sgm_workspace_bytes(H, W, D), dtype=torch.uint8, device=dev)}
+        q = bufs[k]
+        cl, cr = api.census(p["left"]), api.census(p["right"])
+        api.sgm_aggregate(api.cost(cr, cl, D, True, out=q["cost"]), 10, 120, out=q["Sr"], workspace=q["ws"])
+        api.sgm_aggregate(api.cost(cl, cr, D, False, out=q["cost"]), 10, 120, out=q["Sl"], workspace=q["ws"])
+        return api.wta_lr(q["Sl"], q["Sr"], None, 120, 1)
+
+    for p in pairs[:3]:
+        plain_pair(p)
+    torch.cuda.synchronize()
+    e0.record()
+    for p in pairs:
+        r = plain_pair(p)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    # Spot parity: the last pair of each class, batched vs one-by-one.
+    b.run()
+    torch.cuda.synchronize()
+    same = True
+    for (H, W, D) in classes:
+        i = max(j for j, s_ in enumerate(sizes) if s_ == (H, W, D))
+        r = plain_pair(pairs[i])
+        torch.cuda.synchronize()
+        same &= bool(torch.equal(r["valid"], b.out[i]["valid"]) and torch.equal(r["wta_left"], b.out[i]["wta"]))
+    tot = cells(pairs)
+    res = {
+        "metric": "batched plain SGM: whole-batch latency + per-size GCUPS (W·H·D·8 paths/s)",
+        "value": tot / (ms_batch * 1e-3) / 1e9, "unit": "GCUPS", "n_gpus": 1, "steps": steps,
+        "warmup": max(1, args.warmup), "ms_per_step": ms_batch, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "data": "synthetic (seeded piecewise-planar pairs)",
+        "config": {"workload": f"{args.pairs} uneven stereo pairs: 640x480 D=64, 1242x375 D=128, "
+                               "1920x1080 D=256 (pair i has class i mod 3), one HIP graph",
+                   "mem_budget_gb": args.mem_budget_gb, "waves": b.nwaves},
+        "batch_latency_ms": ms_batch, "per_class": per_class, "autotune": tune_info,
+        "plain_one_by_one_ms": ms_plain, "speedup_batched_vs_plain": ms_plain / ms_batch,
+        "spot_parity_batched_equals_one_by_one": same,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     """Learned frame (right views skipped, network mask): fps, speed-up over the
     plain frame, and agreement of its masks with the plain LR check on this frame."""
@@ -121,6 +234,11 @@ def main():
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
                                                     "lrnet_c2.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+                    help="c2: the 1242x375 D=128 scene-flow frame (default); c3: the uneven "
+                         "batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256)")
+    ap.add_argument("--pairs", type=int, default=64, help="pairs in the c3 batch")
+    ap.add_argument("--mem-budget-gb", type=float, default=128.0, help="c3 workspace per wave")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference kernel "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -149,6 +267,8 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": max(args.steps, 1)}), flush=True)
         return
     lib = _lib.lib()
+    if args.workload == "c3":
+        return bench_batch(args, dev)
     H, W, D = 375, 1242, 128
     fr = synth.frame_c2(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
