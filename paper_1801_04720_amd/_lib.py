@@ -10,7 +10,7 @@ import ctypes as ct
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libsf.so")
+LIB_PATH = os.environ.get("SF_LIB_PATH") or os.path.join(_PKG, "libsf.so")
 
 SF_OK, SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP, SF_ENOMEM = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "SF_OK", 1: "SF_EINVAL", 2: "SF_EUNSUPPORTED", 3: "SF_EHIP", 4: "SF_ENOMEM"}

@@ -464,9 +464,162 @@ __global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *
     disp[i] = ok ? dsub[i] : -1.0f;
 }
 
+
+// --- fused inference: all four layers per tile, activations in LDS --------------
+// Output tile FT_H x FT_W; the layer inputs are kept on halos shrinking by one
+// pixel per layer (features 24 x 40, a1 22 x 38, a2 20 x 36, a3 18 x 34).  Pixels
+// of a halo that fall outside the image hold 0 (zero padding of every layer).
+// Layers 1-3 run on v_mfma_f32_16x16x16_bf16 over groups of 16 consecutive
+// pixels of a region (row-major); layer 1 packs 4 taps x 4 channels per K = 16
+// chunk (3 chunks, the last padded with zero weights); layer 4 is VALU.
+// Weight fragments come pre-packed per lane (pack_fused_kernel).
+constexpr int FT_H = 16, FT_W = 32;
+constexpr int FP_L1 = 0, FP_L2 = 3 * 64, FP_L3 = 12 * 64, FP_FRAGS = 21 * 64;  // uint2 slots
+constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_W4 = 48, FP_B4 = 192, FP_FLOATS = 193;
+
+__global__ void pack_fused_kernel(const float *__restrict__ prm, uint2 *__restrict__ frag,
+                                  float *__restrict__ fl)
+{
+    const int lane = threadIdx.x & 63;
+    const int slot = blockIdx.x;  // 0..20
+    const int n = lane & 15, kg = lane >> 4;
+    uint16_t h[4];
+    for (int i = 0; i < 4; ++i) {
+        float w = 0.0f;
+        if (slot < 3) {  // layer 1: tap 4 * slot + kg, channel i
+            const int t = 4 * slot + kg;
+            if (t < 9) w = prm[OFF_W1 + (n * 4 + i) * 9 + t];
+        } else {
+            const int t = (slot - 3) % 9;
+            const int off = slot < 12 ? OFF_W2 : OFF_W3;
+            w = prm[off + (n * 16 + 4 * kg + i) * 9 + t];
+        }
+        h[i] = bf16_bits(w);
+    }
+    frag[slot * 64 + lane] = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                        (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    if (slot == 0) {
+        for (int i = lane; i < FP_FLOATS; i += 64) {
+            float v;
+            if (i < 16) v = prm[OFF_B1 + i];
+            else if (i < 32) v = prm[OFF_B2 + i - 16];
+            else if (i < 48) v = prm[OFF_B3 + i - 32];
+            else if (i < 192) v = bf16_round(prm[OFF_W4 + i - 48]);
+            else v = prm[OFF_B4];
+            fl[i] = v;
+        }
+    }
+}
+
+// One MFMA layer over a region: input sIn [hi][wi][C] (bf16), output sOut [hi-2][wi-2][16];
+// (gy0, gx0) = image coordinates of the output region's first pixel.
+template <int C, int NCH>
+__device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi, uint16_t *sOut,
+                                            const uint2 *__restrict__ frag, float bias, int gy0,
+                                            int gx0, int H, int W, int lane, int wave)
+{
+    const int ho = hi - 2, wo = wi - 2, nout = ho * wo;
+    const int n = lane & 15, kg = lane >> 4;
+    bf16x4 bw[NCH];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const uint2 f = frag[c * 64 + lane];
+        bw[c] = __builtin_bit_cast(bf16x4, f);
+    }
+    const int ngroups = (nout + 15) >> 4;
+    for (int g = wave; g < ngroups; g += 4) {
+        int m = g * 16 + n;
+        if (m >= nout) m = nout - 1;
+        const int oy = m / wo, ox = m - oy * wo;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            bf16x4 a;
+            if (C == 16) {
+                const int ky = c / 3, kx = c % 3;
+                a = *reinterpret_cast<const bf16x4 *>(sIn + (((oy + ky) * wi + ox + kx) * 16 + 4 * kg));
+            } else {
+                const int t = 4 * c + kg;
+                if (t < 9) {
+                    const int ky = t / 3, kx = t % 3;
+                    a = *reinterpret_cast<const bf16x4 *>(sIn + (((oy + ky) * wi + ox + kx) * 4));
+                } else {
+                    a = bf16x4{0, 0, 0, 0};
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[c], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int mo = g * 16 + 4 * kg + i;
+            if (mo >= nout) continue;
+            const int py = mo / wo, px = mo - py * wo;
+            const int gy = gy0 + py, gx = gx0 + px;
+            float v = acc[i] + bias;
+            v = v > 0.0f ? v : 0.0f;
+            if (gy < 0 || gy >= H || gx < 0 || gx >= W) v = 0.0f;
+            sOut[(py * wo + px) * 16 + n] = bf16_bits(v);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void lrnet_fused_kernel(const uint2 *__restrict__ frag,
+                                                          const float *__restrict__ fl,
+                                                          const float4 *__restrict__ feat, int H,
+                                                          int W, float *__restrict__ logits)
+{
+    constexpr int FH = FT_H + 8, FW = FT_W + 8;   // features
+    constexpr int H1 = FT_H + 6, W1 = FT_W + 6;   // a1
+    constexpr int H2 = FT_H + 4, W2 = FT_W + 4;   // a2
+    constexpr int H3 = FT_H + 2, W3 = FT_W + 2;   // a3 (aliases a1)
+    __shared__ __align__(16) uint16_t sF[FH * FW * 4];
+    __shared__ __align__(16) uint16_t sA1[H1 * W1 * 16];
+    __shared__ __align__(16) uint16_t sA2[H2 * W2 * 16];
+    __shared__ float sW4[144];
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * FT_W, y0 = blockIdx.y * FT_H;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const size_t img = (size_t)b * H * W;
+    for (int i = tid; i < FH * FW; i += 256) {
+        const int ly = i / FW, lx = i - ly * FW;
+        const int gy = y0 + ly - 4, gx = x0 + lx - 4;
+        float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) f = feat[img + (size_t)gy * W + gx];
+        reinterpret_cast<uint2 *>(sF)[i] =
+            make_uint2((uint32_t)bf16_bits(f.x) | ((uint32_t)bf16_bits(f.y) << 16),
+                       (uint32_t)bf16_bits(f.z) | ((uint32_t)bf16_bits(f.w) << 16));
+    }
+    for (int i = tid; i < 144; i += 256) sW4[i] = fl[FP_W4 + i];
+    __syncthreads();
+    const int n = lane & 15;
+    fused_layer<4, 3>(sF, FH, FW, sA1, frag + FP_L1, fl[FP_B1 + n], y0 - 3, x0 - 3, H, W, lane, wave);
+    __syncthreads();
+    fused_layer<16, 9>(sA1, H1, W1, sA2, frag + FP_L2, fl[FP_B2 + n], y0 - 2, x0 - 2, H, W, lane, wave);
+    __syncthreads();
+    fused_layer<16, 9>(sA2, H2, W2, sA1, frag + FP_L3, fl[FP_B3 + n], y0 - 1, x0 - 1, H, W, lane, wave);
+    __syncthreads();
+    const float b4 = fl[FP_B4];
+    for (int p = tid; p < FT_H * FT_W; p += 256) {
+        const int oy = p / FT_W, ox = p - oy * FT_W;
+        const int gy = y0 + oy, gx = x0 + ox;
+        if (gy >= H || gx >= W) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+#pragma unroll
+            for (int kx = 0; kx < 3; ++kx) {
+                const uint16_t *a = sA1 + ((oy + ky) * W3 + ox + kx) * 16;
+#pragma unroll
+                for (int ci = 0; ci < 16; ++ci)
+                    acc = __builtin_fmaf(sW4[ci * 9 + ky * 3 + kx], bf16_val(a[ci]), acc);
+            }
+        logits[img + (size_t)gy * W + gx] = acc + b4;
+    }
+}
+
 // --- workspace layout -------------------------------------------------------------
 struct LrLayout {
-    size_t a1, a2, a3, z, g4, gz3, gz2, gz1, part, loss, total;
+    size_t a1, a2, a3, z, g4, gz3, gz2, gz1, part, loss, frag, fl, total;
     int nb4, nbc, npart_max;
 };
 
@@ -481,6 +634,12 @@ static LrLayout lr_layout(int B, int H, int W, bool train)
     L.nb4 = nb4;
     L.nbc = nbc;
     size_t o = 0;
+    L.frag = o; o += al(FP_FRAGS * 8);
+    L.fl = o; o += al(FP_FLOATS * 4);
+    if (!train) {  // fused inference keeps activations on chip
+        L.total = o;
+        return L;
+    }
     L.a1 = o; o += al(npx * 32);
     L.a2 = o; o += al(npx * 32);
     L.a3 = o; o += al(npx * 32);
@@ -556,8 +715,15 @@ namespace sf {
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
                   uint8_t *ws, hipStream_t st)
 {
-    return lr_forward(params, feat, B, H, W, ws, lr_layout(B, H, W, false), logits, nullptr, nullptr,
-                      nullptr, st);
+    const LrLayout L = lr_layout(B, H, W, false);
+    uint2 *frag = reinterpret_cast<uint2 *>(ws + L.frag);
+    float *fl = reinterpret_cast<float *>(ws + L.fl);
+    ProfScope prof("lrnet_fused", st);
+    hipLaunchKernelGGL(pack_fused_kernel, dim3(21), dim3(64), 0, st, params, frag, fl);
+    dim3 g((W + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H, B);
+    hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(256), 0, st, frag, fl,
+                       reinterpret_cast<const float4 *>(feat), H, W, logits);
+    return launch_status("lrnet_fused_kernel");
 }
 
 int launch_lr_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
@@ -578,9 +744,8 @@ extern "C" int sf_lrnet_forward(const float *params, const float *feat, int B, i
     int rc = lr_check(params, feat, B, H, W, workspace, ws_bytes, false);
     if (rc) return rc;
     SF_REQUIRE(logits, SF_EINVAL, "sf_lrnet_forward: NULL logits");
-    const LrLayout L = lr_layout(B, H, W, false);
-    return lr_forward(params, feat, B, H, W, static_cast<uint8_t *>(workspace), L, logits, nullptr,
-                      nullptr, nullptr, as_stream(stream));
+    return lrnet_forward(params, feat, B, H, W, logits, static_cast<uint8_t *>(workspace),
+                         as_stream(stream));
 }
 
 extern "C" int sf_lrnet_mask(const float *logits, const int16_t *wta, const float *dsub, int H,
