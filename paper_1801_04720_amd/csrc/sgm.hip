@@ -6,10 +6,15 @@
 //   * one "path chain" = one scanline of one direction, walked from the image
 //     edge where its predecessor leaves the image;
 //   * a chain is owned by one 16-lane DPP row; lane j of the row holds the K =
-//     D/16 consecutive disparities [jK, jK+K) as K/2 packed u16 pairs, so the
-//     d-1 / d+1 neighbours come from v_alignbit inside a lane plus one
-//     row_shr / row_shl DPP move across lanes, and min_k Lr(p-r, k) is a
-//     4-step DPP butterfly inside the row (quad_perm, half-mirror, mirror);
+//     D/16 disparities [jK, jK+K) as K/2 packed u16 pairs, interleaved: pair i
+//     holds d = jK + i (low half) and d = jK + K/2 + i (high half).  Then the
+//     d-1 neighbours of pair i are exactly pair i-1 and the d+1 neighbours pair
+//     i+1; only the two end pairs need a v_alignbit with one row_shr / row_shl
+//     DPP move across lanes.  min_k Lr(p-r, k) is a 4-step DPP butterfly inside
+//     the row (quad_perm, half-mirror, mirror);
+//   * slabs keep each lane's K bytes in the same interleaved order (byte 2i =
+//     pair i low, byte 2i+1 = pair i high): position e of lane j's chunk holds
+//     d = jK + e/2 + (e%2) K/2.  Their consumers map positions back to d.
 //   * a wave carries 4 chains, a 256-thread block 16.
 //   * Lr needs at most 62 + P2 <= 255 (u8) when P2 <= 193: each direction's
 //     Lr is then streamed to its own u8 slab and the consumer sums the slabs
@@ -104,19 +109,55 @@ __device__ __forceinline__ void load_raw(const uint8_t *p, CostRaw<K> &r)
     }
 }
 
+// The same through a raw buffer resource: 32-bit offsets, and offsets past the
+// volume (steps beyond a chain's end) read zeros instead of faulting.
+constexpr int SGM_RSRC_WORD3 = 0x00020000;  // raw buffer, gfx9-family data format
+
+template <int K>
+__device__ __forceinline__ void load_raw_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, CostRaw<K> &r)
+{
+    if constexpr (K % 16 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 16; ++q) {
+            const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0));
+            r.w[4 * q + 0] = v.x;
+            r.w[4 * q + 1] = v.y;
+            r.w[4 * q + 2] = v.z;
+            r.w[4 * q + 3] = v.w;
+        }
+    } else if constexpr (K % 8 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 8; ++q) {
+            const u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(off + 8 * q), 0, 0));
+            r.w[2 * q + 0] = v.x;
+            r.w[2 * q + 1] = v.y;
+        }
+    } else if constexpr (K % 4 == 0) {
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) r.w[q] = __builtin_amdgcn_raw_buffer_load_b32(rs, (int)(off + 4 * q), 0, 0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q)
+            r.w[q] = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(rs, (int)(off + 2 * q), 0, 0);
+    }
+}
+
+// Cost bytes (d order) -> interleaved u16 pairs: pair i = (d = jK + i, d = jK + K/2 + i).
 template <int K>
 __device__ __forceinline__ void unpack(const CostRaw<K> &r, uint32_t (&c)[K / 2])
 {
-    if constexpr (K % 4 == 0) {
 #pragma unroll
-        for (int q = 0; q < K / 4; ++q) {
-            // bytes b0 b1 b2 b3 -> (b0, b1) and (b2, b3) as u16 pairs
-            c[2 * q + 0] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c010c00u);
-            c[2 * q + 1] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c030c02u);
+    for (int i = 0; i < K / 2; ++i) {
+        const int lo = i, hi = K / 2 + i;
+        if constexpr (K % 4 == 0) {
+            const uint32_t sel = (uint32_t)(lo % 4) | (0x0cu << 8) | ((uint32_t)(4 + hi % 4) << 16) |
+                                 (0x0cu << 24);
+            c[i] = __builtin_amdgcn_perm(r.w[hi / 4], r.w[lo / 4], sel);
+        } else {
+            const uint32_t sel = (uint32_t)(lo % 2) | (0x0cu << 8) | ((uint32_t)(4 + hi % 2) << 16) |
+                                 (0x0cu << 24);
+            c[i] = __builtin_amdgcn_perm(r.w[hi / 2], r.w[lo / 2], sel);
         }
-    } else {
-#pragma unroll
-        for (int q = 0; q < K / 2; ++q) c[q] = __builtin_amdgcn_perm(0u, r.w[q], 0x0c010c00u);
     }
 }
 
@@ -124,9 +165,18 @@ template <int K, bool ATOMIC>
 __device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_px, uint16_t *s_px)
 {
     if constexpr (ATOMIC) {
+        // Back to d order: word m holds d = jK + 2m and jK + 2m + 1; relative d
+        // below K/2 sits in the low half of pair d, the rest in the high half of
+        // pair d - K/2.
         uint32_t *s32 = reinterpret_cast<uint32_t *>(s_px);
+        constexpr int NP = K / 2;
 #pragma unroll
-        for (int i = 0; i < K / 2; ++i) atomicAdd(s32 + i, L[i]);
+        for (int m = 0; m < NP; ++m) {
+            const int d0 = 2 * m, d1 = 2 * m + 1;
+            const int p0 = d0 < NP ? d0 : d0 - NP, p1 = d1 < NP ? d1 : d1 - NP;
+            const uint32_t sel = (d0 < NP ? 0x0100u : 0x0302u) | (d1 < NP ? 0x05040000u : 0x07060000u);
+            atomicAdd(s32 + m, __builtin_amdgcn_perm(L[p1], L[p0], sel));
+        }
     } else {
         // Low byte of each u16 half -> K consecutive bytes.
         if constexpr (K % 4 == 0) {
@@ -161,6 +211,39 @@ __device__ __forceinline__ void emit(const uint32_t (&L)[K / 2], uint8_t *slab_p
     }
 }
 
+// Slab store through a buffer resource (32-bit offsets), non-temporal: slabs are
+// written once and read once, much later, so they should not evict the cost
+// volumes from the caches.
+template <int K>
+__device__ __forceinline__ void emit_buf(const uint32_t (&L)[K / 2], __amdgpu_buffer_rsrc_t rs,
+                                         uint32_t off)
+{
+    constexpr int NT = 2;  // non-temporal
+    if constexpr (K % 4 == 0) {
+        uint32_t b[K / 4];
+#pragma unroll
+        for (int q = 0; q < K / 4; ++q) b[q] = __builtin_amdgcn_perm(L[2 * q + 1], L[2 * q], 0x06040200u);
+        if constexpr (K % 16 == 0) {
+#pragma unroll
+            for (int q = 0; q < K / 16; ++q)
+                __builtin_amdgcn_raw_buffer_store_b128(u32x4{b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]},
+                                                       rs, (int)(off + 16 * q), 0, NT);
+        } else if constexpr (K % 8 == 0) {
+#pragma unroll
+            for (int q = 0; q < K / 8; ++q)
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{b[2 * q], b[2 * q + 1]}, rs, (int)(off + 8 * q), 0, NT);
+        } else {
+#pragma unroll
+            for (int q = 0; q < K / 4; ++q) __builtin_amdgcn_raw_buffer_store_b32(b[q], rs, (int)(off + 4 * q), 0, NT);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < K / 2; ++q)
+            __builtin_amdgcn_raw_buffer_store_b16((uint16_t)__builtin_amdgcn_perm(0u, L[q], 0x0c0c0200u), rs,
+                                                  (int)(off + 2 * q), 0, NT);
+    }
+}
+
 // Default prefetch depth (steps) of the cost stream of one chain.
 constexpr int SGM_U = 8;
 
@@ -180,57 +263,71 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     // Byte step along the chain in the [H][W][D] volumes.
     const ptrdiff_t bstep = ((ptrdiff_t)ry * W + rx) * D;
     const size_t b0 = ((size_t)y * W + x) * D + (size_t)j * K;
-    const uint8_t *ld = cost + b0;                               // next cost load
-    uint8_t *st = ATOMIC ? nullptr : slab + b0;                  // next slab store
+    // Cost volume through a buffer resource (the volume is < 2^31 bytes).
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(cost), (short)0, (int)((size_t)H * W * D), SGM_RSRC_WORD3);
+    uint32_t ld = (uint32_t)b0;                                  // next cost load (offset)
+    const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(
+        ATOMIC ? (void *)S : (void *)slab, (short)0, (int)((size_t)H * W * D), SGM_RSRC_WORD3);
+    uint32_t st = (uint32_t)b0;                                  // next slab store (offset)
     uint16_t *stS = ATOMIC ? S + b0 : nullptr;                   // next S update
 
     const u16x2 vP1 = (u16x2)((unsigned short)P1);
+    // Path start: with Lr(p - r, .) = 0 and M = 0 the recurrence gives exactly
+    // Lr(p, d) = C(p, d) (every candidate of the min is >= 0 and Lr(d) = 0), so
+    // the first step needs no special case.
     uint32_t L[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) L[i] = 0;
     uint32_t M = 0;
     // Loop-carried DPP destinations: the lanes with no source in the row (lane 0
     // for row_shr, lane 15 for row_shl) keep the "no neighbour" value forever.
     uint32_t below = SGM_SENT, above = SGM_SENT;
-
+    // Steps past the end of this chain (other chains of the wave may be longer)
+    // load whatever the buffer holds there (zeros beyond it) and store nothing.
     auto fetch = [&](int t0, CostRaw<K>(&buf)[U]) {
+        (void)t0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (t0 + u < len) load_raw<K>(ld, buf[u]);
-            ld += bstep;
+            load_raw_buf<K>(rs, ld, buf[u]);
+            ld += (uint32_t)bstep;
         }
     };
     auto step = [&](int t, const CostRaw<K> &raw) {
-        if (t >= len) return;
         uint32_t c[NP];
         unpack<K>(raw, c);
-        if (t == 0) {
+        below = dpp_fill<DPP_ROW_SHR1>(below, L[NP - 1]);
+        above = dpp_fill<DPP_ROW_SHL1>(above, L[0]);
+        const u16x2 vM = (u16x2)((unsigned short)M);
+        const u16x2 vMP2 = (u16x2)((unsigned short)(M + P2));
+        uint32_t nL[NP];
 #pragma unroll
-            for (int i = 0; i < NP; ++i) L[i] = c[i];
-        } else {
-            below = dpp_fill<DPP_ROW_SHR1>(below, L[NP - 1]);
-            above = dpp_fill<DPP_ROW_SHL1>(above, L[0]);
-            const u16x2 vM = (u16x2)((unsigned short)M);
-            const u16x2 vMP2 = (u16x2)((unsigned short)(M + P2));
-            uint32_t nL[NP];
-#pragma unroll
-            for (int i = 0; i < NP; ++i) {
-                const uint32_t lo_nb = (i == 0) ? below : L[i - 1];
-                const uint32_t hi_nb = (i == NP - 1) ? above : L[i + 1];
-                const u16x2 minus = as_u16x2(__builtin_amdgcn_alignbit(L[i], lo_nb, 16));
-                const u16x2 plus = as_u16x2(__builtin_amdgcn_alignbit(hi_nb, L[i], 16));
-                u16x2 tt = __builtin_elementwise_min(minus, plus) + vP1;
-                tt = __builtin_elementwise_min(tt, as_u16x2(L[i]));
-                tt = __builtin_elementwise_min(tt, vMP2);
-                tt = tt - vM + as_u16x2(c[i]);
-                nL[i] = as_u32(tt);
-            }
-#pragma unroll
-            for (int i = 0; i < NP; ++i) L[i] = nL[i];
+        for (int i = 0; i < NP; ++i) {
+            // Interleaved pairs: d-1 of pair i is pair i-1, d+1 is pair i+1;
+            // pair 0's low half needs lane j-1's last pair (high half), and
+            // the last pair's high half needs lane j+1's first pair (low half).
+            const u16x2 minus = as_u16x2(
+                i == 0 ? __builtin_amdgcn_alignbit(L[NP - 1], below, 16) : L[i - 1]);
+            const u16x2 plus = as_u16x2(
+                i == NP - 1 ? __builtin_amdgcn_alignbit(above, L[0], 16) : L[i + 1]);
+            u16x2 tt = __builtin_elementwise_min(minus, plus) + vP1;
+            tt = __builtin_elementwise_min(tt, as_u16x2(L[i]));
+            tt = __builtin_elementwise_min(tt, vMP2);
+            tt = tt - vM + as_u16x2(c[i]);
+            nL[i] = as_u32(tt);
         }
-        emit<K, ATOMIC>(L, st, stS);
+#pragma unroll
+        for (int i = 0; i < NP; ++i) L[i] = nL[i];
+        if (t < len) {
+            if constexpr (ATOMIC)
+                emit<K, true>(L, nullptr, stS);
+            else
+                emit_buf<K>(L, rs_out, st);
+        }
         if constexpr (ATOMIC)
             stS += bstep;
         else
-            st += bstep;
+            st += (uint32_t)bstep;
         u16x2 m2 = as_u16x2(L[0]);
 #pragma unroll
         for (int i = 1; i < NP; ++i) m2 = __builtin_elementwise_min(m2, as_u16x2(L[i]));
@@ -301,32 +398,33 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
     }
 }
 
-// S[i] = sum over the n slabs of slab[k][i]; 16 cells per thread.
+// S[p][d] = sum over the n slabs; one thread per (pixel, lane chunk of K
+// bytes), undoing the interleaved order of the chunk (position e <-> d = jK +
+// e/2 + (e%2) K/2).
+template <int K>
 __global__ __launch_bounds__(256) void slab_sum_kernel(const uint8_t *__restrict__ slab, int n,
-                                                       size_t ncell, uint16_t *__restrict__ S)
+                                                       size_t npx, uint16_t *__restrict__ S)
 {
-    const size_t i = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
-    if (i >= ncell) return;
-    if (i + 16 <= ncell) {
-        uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // u16 pairs
-        for (int k = 0; k < n; ++k) {
-            uint4 v = *reinterpret_cast<const uint4 *>(slab + (size_t)k * ncell + i);
-            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    constexpr int D = 16 * K, NP = K / 2;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npx * 16) return;
+    const size_t p = t >> 4;
+    const int j = (int)(t & 15);
+    const size_t cells = npx * D;
+    const size_t off = p * D + (size_t)j * K;
+    uint32_t acc[NP];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                acc[2 * q] += __builtin_amdgcn_perm(0u, w[q], 0x0c010c00u);
-                acc[2 * q + 1] += __builtin_amdgcn_perm(0u, w[q], 0x0c030c02u);
-            }
-        }
-        uint4 *o = reinterpret_cast<uint4 *>(S + i);
-        o[0] = make_uint4(acc[0], acc[1], acc[2], acc[3]);
-        o[1] = make_uint4(acc[4], acc[5], acc[6], acc[7]);
-    } else {
-        for (size_t c = i; c < ncell; ++c) {
-            uint32_t s = 0;
-            for (int k = 0; k < n; ++k) s += slab[(size_t)k * ncell + c];
-            S[c] = (uint16_t)s;
-        }
+    for (int i = 0; i < NP; ++i) acc[i] = 0;
+    for (int k = 0; k < n; ++k) {
+        const uint8_t *src = slab + (size_t)k * cells + off;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) acc[i] += (uint32_t)src[2 * i] | ((uint32_t)src[2 * i + 1] << 16);
+    }
+    uint16_t *dst = S + off;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+        dst[i] = (uint16_t)(acc[i] & 0xFFFFu);
+        dst[NP + i] = (uint16_t)(acc[i] >> 16);
     }
 }
 
@@ -520,9 +618,19 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     }
     int rc = launch_status("sgm_paths_kernel");
     if (rc || atomic) return rc;
-    const size_t nthr = (ncell + 15) / 16;
+    const size_t npx = (size_t)H * W;
+    const unsigned nblk_sum = (unsigned)((npx * 16 + 255) / 256);
     ProfScope prof("slab_sum", st);
-    hipLaunchKernelGGL(slab_sum_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st,
-                       slab, tab.ndir, ncell, S);
+    switch (D / 16) {
+#define SF_SUM_CASE(KK)                                                                        \
+    case KK:                                                                                   \
+        hipLaunchKernelGGL(slab_sum_kernel<KK>, dim3(nblk_sum), dim3(256), 0, st, slab, tab.ndir, \
+                           npx, S);                                                            \
+        break;
+        SF_SUM_CASE(2) SF_SUM_CASE(4) SF_SUM_CASE(6) SF_SUM_CASE(8) SF_SUM_CASE(10) SF_SUM_CASE(12)
+        SF_SUM_CASE(14) SF_SUM_CASE(16)
+#undef SF_SUM_CASE
+    default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
+    }
     return launch_status("slab_sum_kernel");
 }

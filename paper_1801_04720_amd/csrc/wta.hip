@@ -104,8 +104,18 @@ __global__ __launch_bounds__(WTA_NT) void wta_left_kernel(
 }
 
 // WTA on S = sum of u8 slabs, summed on the fly (S is never written).  Lane j
-// holds disparity chunks [8c, 8c + 8), c = j and j + 16, as packed u16 sums;
-// each slab load is 8 bytes per lane, 128 contiguous bytes per pixel row.
+// holds slab byte positions [8c, 8c + 8), c = j and j + 16, as packed u16 sums;
+// each slab load is 8 bytes per lane, 128 contiguous bytes per pixel row.  The
+// aggregation stores each 16-lane chunk of K = D/16 bytes interleaved: position
+// e of chunk q holds d = qK + e/2 + (e%2) K/2.
+template <int K>
+__device__ __forceinline__ int slab_pos_to_d(int pos)
+{
+    const int q = pos / K, e = pos - q * K;
+    return q * K + (e >> 1) + (e & 1) * (K >> 1);
+}
+
+template <int K>
 __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 {
     int vi = 0;
@@ -115,15 +125,18 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
     const int px = ((int)blockIdx.x - a.blk0[vi]) * WTA_PPB + q;
     const int npx = v.H * v.W;
     if (px >= npx) return;
-    const int D = v.D;
+    constexpr int D = 16 * K;
     const size_t cells = (size_t)npx * D;
     uint32_t sv[2][4];
+    int dd[2][8];
     uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
 #pragma unroll
         for (int e = 0; e < 4; ++e) sv[i][e] = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dd[i][e] = slab_pos_to_d<K>(8 * c + e);
         if (8 * c < D) {
             const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
             for (int k = 0; k < v.nslab; ++k) {
@@ -137,7 +150,7 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
-                best = min(best, (val << 9) | (uint32_t)(8 * c + e));
+                best = min(best, (val << 9) | (uint32_t)dd[i][e]);
             }
         }
     }
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         if (8 * c < D) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int d = 8 * c + e;
+                const int d = dd[i][e];
                 const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
                 if (d == ds - 1) av = val;
                 if (d == ds + 1) cv = val;
@@ -208,8 +221,19 @@ int launch_wta_slabs(WtaArgs &a, hipStream_t st)
     for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
     if (tot <= 0) return SF_OK;
     if (tot > 0x7FFFFFFFLL) return fail(SF_EINVAL, "launch_wta_slabs: grid too large");
+    for (int i = 1; i < a.n; ++i)
+        if (a.v[i].D != a.v[0].D) return fail(SF_EINVAL, "launch_wta_slabs: views of one launch need one D");
     ProfScope prof(a.v[0].right_only ? "wta_slab_right" : "wta_slab_left", st);
-    hipLaunchKernelGGL(wta_slab_kernel, dim3((unsigned)tot), dim3(WTA_NT), 0, st, a);
+    switch (a.v[0].D / 16) {
+#define SF_WTA_CASE(KK)                                                                             \
+    case KK:                                                                                        \
+        hipLaunchKernelGGL(wta_slab_kernel<KK>, dim3((unsigned)tot), dim3(WTA_NT), 0, st, a);        \
+        break;
+        SF_WTA_CASE(2) SF_WTA_CASE(4) SF_WTA_CASE(6) SF_WTA_CASE(8) SF_WTA_CASE(10) SF_WTA_CASE(12)
+        SF_WTA_CASE(14) SF_WTA_CASE(16)
+#undef SF_WTA_CASE
+    default: return fail(SF_EUNSUPPORTED, "launch_wta_slabs: unsupported D");
+    }
     return launch_status("wta_slab_kernel");
 }
 
