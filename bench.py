@@ -99,7 +99,8 @@ def bench_batch(args, dev):
             classes.append(s_)
     tunings, tune_info = {}, {}
     for (H, W, D) in classes:
-        t, ms = batch.autotune(H, W, D, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+        t, ms = batch.autotune(H, W, D, nviews=2,
+                               cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
         tunings[(H, W, D)] = t
         tune_info[f"{W}x{H}xD{D}"] = dict(batch.tuning_dict(t), aggregation_ms_per_pair=ms)
     budget = int(args.mem_budget_gb * (1 << 30))
@@ -200,7 +201,13 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     else:
         prm = lrnet.init_params(0)
     prm_t = torch.from_numpy(prm).to(dev)
-    lp = FusedFrame(H, W, D, learned_params=prm_t, device=dev)
+    tuning = None
+    if not args.no_autotune:
+        from paper_1801_04720_amd import batch
+
+        tuning, _ = batch.autotune(H, W, D, nviews=2,
+                                   cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+    lp = FusedFrame(H, W, D, learned_params=prm_t, tuning=tuning, device=dev)
     for _ in range(args.warmup):
         lp.run(*inputs)
     torch.cuda.synchronize()
@@ -231,6 +238,8 @@ def main():
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default aggregation tuning instead of the autotuner's choice")
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
                                                     "lrnet_c2.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
@@ -274,10 +283,17 @@ def main():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     L0, R0, L1, R1, flow = t(fr.t0.left), t(fr.t0.right), t(fr.t1.left), t(fr.t1.right), t(fr.flow)
     api.sgm_set_epilogue(args.epilogue)
+    tuning, tuning_info = None, None
+    if args.pipeline != "stages" and not args.no_autotune:
+        from paper_1801_04720_amd import batch
+
+        tuning, t_ms = batch.autotune(H, W, D, nviews=4,
+                                      cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+        tuning_info = dict(batch.tuning_dict(tuning), tuner_ms=t_ms)
     if args.pipeline == "stages":
         pipe = PlainFrame(H, W, D, device=dev)
     else:
-        pipe = FusedFrame(H, W, D, persistent=args.pipeline == "persistent", device=dev)
+        pipe = FusedFrame(H, W, D, persistent=args.pipeline == "persistent", tuning=tuning, device=dev)
     for _ in range(args.warmup):
         pipe.run(L0, R0, L1, R1, flow)
     torch.cuda.synchronize()
@@ -338,7 +354,8 @@ def main():
         "config": {"workload": "plain scene-flow frame 1242x375 D=128 (SGM t0+t1 incl. right "
                                "views and LR check, combination, triangulation)",
                    "H": H, "W": W, "D": D, "paths": 8, "P1": 10, "P2": 120, "lr_tol": 1,
-                   "epilogue": args.epilogue, "pipeline": args.pipeline},
+                   "epilogue": args.epilogue, "pipeline": args.pipeline,
+                   "aggregation_tuning": tuning_info},
         "fps_plain": 1e3 / ms,
         "gcups_all_passes": gcups_passes,
         "lr_valid_frac_t0": valid0,

@@ -158,6 +158,17 @@ int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
  * captured in a HIP graph.  A plan may be run concurrently on different
  * streams only with different workspaces. */
 typedef struct sf_plan_s *sf_plan;
+
+/* Tuning of the multi-view aggregation launch (frame and batch plans):
+ *   chains_per_block  4, 8 or 16 chains (16-lane rows) per block
+ *   prefetch          4 or 8 cost steps in flight per chain
+ *   order             0 = tasks longest chains first, 1 = view by view
+ *   persistent_per_cu 0 = one block per task; k > 0 = k blocks per CU pulling
+ *                     tasks from a counter
+ * Every tuning gives identical results. */
+typedef struct {
+    int chains_per_block, prefetch, order, persistent_per_cu;
+} sf_agg_tuning;
 size_t sf_plan_workspace_bytes(sf_plan plan);
 int sf_plan_destroy(sf_plan plan);
 
@@ -175,7 +186,7 @@ int sf_plan_destroy(sf_plan plan);
 #define SF_FRAME_PERSISTENT 1
 #define SF_FRAME_LEARNED 2
 int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
-                         sf_plan *plan);
+                         const sf_agg_tuning *tuning /* host, NULL = default */, sf_plan *plan);
 /* L0, R0, L1, R1 [H][pitch] uint8; flow [H][W][2]; cam host pointer or NULL.
  * Outputs: disp0/valid0 (t0 map), disp1/valid1 (t1 map), as sf_wta_lr;
  * sf4/valid/xyz0/motion as sf_combine.  Errors: SF_EINVAL, SF_ENOMEM
@@ -206,13 +217,8 @@ int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, con
  * one wave); each wave runs one aggregation launch per size class from a
  * device task table.  Device pointers in the pair descriptors are fixed at plan
  * creation and must stay valid while the plan is used.
- * Tuning of the aggregation per size class (classes numbered in order of first
- * appearance in `pairs`; NULL / missing = {16, 8, 0, 0}):
- *   chains_per_block  4, 8 or 16 chains (16-lane rows) per block
- *   prefetch          4 or 8 cost steps in flight per chain
- *   order             0 = tasks longest chains first, 1 = view by view
- *   persistent_per_cu 0 = one block per task; k > 0 = k blocks per CU pulling
- *                     tasks from a counter
+ * Tuning of the aggregation per size class (sf_agg_tuning; classes numbered in
+ * order of first appearance in `pairs`; NULL / missing = {16, 8, 0, 0}).
  * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (table upload). */
 typedef struct {
@@ -222,10 +228,6 @@ typedef struct {
     float *disp;                 /* [H][W] d_sub or -1 */
     uint8_t *valid;              /* [H][W] LR-check mask */
 } sf_pair;
-
-typedef struct {
-    int chains_per_block, prefetch, order, persistent_per_cu;
-} sf_agg_tuning;
 
 int sf_batch_plan_create(const sf_pair *pairs /* host array */, int n, int P1, int P2, int lr_tol,
                          const sf_agg_tuning *tunings /* host, per class */, int ntunings,
@@ -238,11 +240,12 @@ int sf_batch_run(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
 int sf_batch_capture(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
 int sf_batch_launch(sf_plan plan, void *stream);
 /* Autotuner: times every candidate tuning (chains per block x prefetch x order x
- * persistence) of the aggregation of one H x W x D pair (both views, synthetic
- * costs) on `stream`, and returns the fastest and its median time.  Allocates
- * and frees its own scratch; synchronises the stream. */
-int sf_agg_autotune(int H, int W, int D, int P1, int P2, void *stream, sf_agg_tuning *best,
-                    float *best_ms);
+ * persistence) of one aggregation launch over nviews views of H x W x D
+ * (synthetic costs; 2 = a stereo pair, 4 = a scene-flow frame) on `stream`, and
+ * returns the fastest and its median time.  Allocates and frees its own
+ * scratch; synchronises the stream. */
+int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, void *stream,
+                    sf_agg_tuning *best, float *best_ms);
 
 /* ---------------------------------------------------------------------------
  * Learned stand-in for the left-right check (the check is the paper's, Sec.

@@ -56,7 +56,7 @@ SIGNATURES = {
     "sf_combine": (I, [P, P, P, P, P, I, I, ct.POINTER(SfCamera), P, P, P, P, P]),
     "sf_plan_workspace_bytes": (SZ, [P]),
     "sf_plan_destroy": (I, [P]),
-    "sf_frame_plan_create": (I, [I, I, I, I, I, I, I, ct.POINTER(P)]),
+    "sf_frame_plan_create": (I, [I, I, I, I, I, I, I, ct.POINTER(SfAggTuning), ct.POINTER(P)]),
     "sf_frame_run": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P, P, SZ,
                          P]),
     "sf_lrnet_nparams": (I, []),
@@ -73,7 +73,7 @@ SIGNATURES = {
     "sf_batch_run": (I, [P, P, SZ, P]),
     "sf_batch_capture": (I, [P, P, SZ, P]),
     "sf_batch_launch": (I, [P, P]),
-    "sf_agg_autotune": (I, [I, I, I, I, I, P, ct.POINTER(SfAggTuning), ct.POINTER(F)]),
+    "sf_agg_autotune": (I, [I, I, I, I, I, I, P, ct.POINTER(SfAggTuning), ct.POINTER(F)]),
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),

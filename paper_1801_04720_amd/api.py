@@ -165,10 +165,12 @@ FRAME_PERSISTENT, FRAME_LEARNED = 1, 2
 
 
 def frame_plan(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
-               persistent: bool = False, learned: bool = False) -> Plan:
+               persistent: bool = False, learned: bool = False, tuning=None) -> Plan:
+    """tuning: an _lib.SfAggTuning for the aggregation launch (None = default)."""
     h = ct.c_void_p()
     flags = (FRAME_PERSISTENT if persistent else 0) | (FRAME_LEARNED if learned else 0)
-    check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, ct.byref(h)))
+    tp = ct.byref(tuning) if tuning is not None else None
+    check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, tp, ct.byref(h)))
     return Plan(h)
 
 

@@ -31,9 +31,10 @@ def tuning_dict(t: SfAggTuning) -> dict:
 
 
 def autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, cache: str | None = DEFAULT_CACHE,
-             stream=None, refresh: bool = False) -> tuple[SfAggTuning, float | None]:
-    """Fastest aggregation tuning for one H x W x D pair (cached per arch and size)."""
-    key = f"{_arch()}:{H}x{W}x{D}:P1={P1}:P2={P2}"
+             stream=None, refresh: bool = False, nviews: int = 2) -> tuple[SfAggTuning, float | None]:
+    """Fastest aggregation tuning for nviews views of H x W x D (2 = a stereo pair,
+    4 = a scene-flow frame), cached per arch, size and view count."""
+    key = f"{_arch()}:{H}x{W}x{D}:P1={P1}:P2={P2}" + (f":views={nviews}" if nviews != 2 else "")
     db = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
@@ -43,7 +44,7 @@ def autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, cache: str | N
         return SfAggTuning(e["chains_per_block"], e["prefetch"], e["order"], e["persistent_per_cu"]), e.get("ms")
     best = SfAggTuning()
     ms = ct.c_float(0.0)
-    check(lib().sf_agg_autotune(H, W, D, P1, P2, _stream(stream), ct.byref(best), ct.byref(ms)))
+    check(lib().sf_agg_autotune(H, W, D, P1, P2, nviews, _stream(stream), ct.byref(best), ct.byref(ms)))
     if cache:
         db[key] = dict(tuning_dict(best), ms=float(ms.value))
         os.makedirs(os.path.dirname(cache), exist_ok=True)

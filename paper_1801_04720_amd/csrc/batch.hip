@@ -392,7 +392,7 @@ void destroy_batch(BatchData *b)
 }
 }  // namespace sf
 
-extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, void *stream,
+extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, void *stream,
                                sf_agg_tuning *best, float *best_ms)
 {
     clear_error();
@@ -400,14 +400,15 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, void *stream
     SF_REQUIRE(H > 0 && W > 0 && (long long)H * W <= (1LL << 28), SF_EINVAL, "sf_agg_autotune: bad size");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED, "sf_agg_autotune: bad D");
     SF_REQUIRE(P1 >= 0 && P2 >= P1 && SF_CMAX + P2 <= 255, SF_EINVAL, "sf_agg_autotune: bad P1/P2");
+    SF_REQUIRE(nviews >= 1 && nviews <= 8, SF_EINVAL, "sf_agg_autotune: nviews must be in [1, 8]");
     hipStream_t st = as_stream(stream);
-    // One pair (left and right view) of synthetic costs.
-    const PairLayout L = pair_layout(H, W, D);
-    uint8_t *ws = nullptr;
-    if (hipMalloc(&ws, L.total) != hipSuccess) return fail(SF_EHIP, "sf_agg_autotune: hipMalloc");
+    // nviews views of synthetic costs, each with its cost volume and 8 slabs.
     const size_t ncell = (size_t)H * W * D;
-    for (int v = 0; v < 2; ++v)
-        hipLaunchKernelGGL(fill_random_cost_kernel, dim3(4096), dim3(256), 0, st, ws + L.cost[v], ncell,
+    const size_t vbytes = al256(ncell) + al256(8 * ncell);
+    uint8_t *ws = nullptr;
+    if (hipMalloc(&ws, vbytes * nviews) != hipSuccess) return fail(SF_EHIP, "sf_agg_autotune: hipMalloc");
+    for (int v = 0; v < nviews; ++v)
+        hipLaunchKernelGGL(fill_random_cost_kernel, dim3(4096), dim3(256), 0, st, ws + v * vbytes, ncell,
                            1234u + v);
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
@@ -421,10 +422,10 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, void *stream
             std::vector<AggView> views;
             std::vector<AggTask> tasks;
             std::vector<int> lens;
-            for (int side = 0; side < 2; ++side) {
+            for (int side = 0; side < nviews; ++side) {
                 AggView v{};
-                v.cost_off = L.cost[side];
-                v.slab_off = L.slab[side];
+                v.cost_off = side * vbytes;
+                v.slab_off = side * vbytes + al256(ncell);
                 v.H = H; v.W = W; v.K = D / 16; v.P1 = P1; v.P2 = P2; v.ndir = 8;
                 for (int r = 0; r < 8; ++r) v.dir[r] = r;
                 append_agg_tasks(tasks, lens, side, v, cpb);

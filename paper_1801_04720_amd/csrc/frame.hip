@@ -36,12 +36,12 @@ int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::ve
     return SF_OK;
 }
 
-int default_persistent_blocks()
+int cu_count_dev()
 {
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return ncu * 8;  // 8 blocks of 4 waves per CU
+    return ncu;
 }
 
 }  // namespace sf
@@ -49,7 +49,7 @@ int default_persistent_blocks()
 using namespace sf;
 
 extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
-                                    sf_plan *out)
+                                    const sf_agg_tuning *tuning, sf_plan *out)
 {
     clear_error();
     SF_REQUIRE(out, SF_EINVAL, "sf_frame_plan_create: NULL out");
@@ -65,6 +65,17 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
                "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
     SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED)) == 0, SF_EINVAL,
                "sf_frame_plan_create: unknown flags");
+    sf_agg_tuning tun{16, 8, 0, (flags & SF_FRAME_PERSISTENT) ? 8 : 0};
+    if (tuning) {
+        tun = *tuning;
+        SF_REQUIRE(tun.chains_per_block == 4 || tun.chains_per_block == 8 || tun.chains_per_block == 16,
+                   SF_EINVAL, "sf_frame_plan_create: chains_per_block must be 4, 8 or 16");
+        SF_REQUIRE(tun.prefetch == 4 || tun.prefetch == 8, SF_EINVAL,
+                   "sf_frame_plan_create: prefetch must be 4 or 8");
+        SF_REQUIRE(tun.order == 0 || tun.order == 1, SF_EINVAL, "sf_frame_plan_create: order must be 0 or 1");
+        SF_REQUIRE(tun.persistent_per_cu >= 0 && tun.persistent_per_cu <= 32, SF_EINVAL,
+                   "sf_frame_plan_create: persistent_per_cu must be in [0, 32]");
+    }
     Plan *p = new (std::nothrow) Plan();
     if (!p) return fail(SF_ENOMEM, "sf_frame_plan_create: out of host memory");
     p->kind = Plan::FRAME;
@@ -106,15 +117,16 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
         v.P2 = P2;
         v.ndir = 8;
         for (int r = 0; r < 8; ++r) v.dir[r] = r;
-        append_agg_tasks(tasks, lens, i, v);
+        append_agg_tasks(tasks, lens, i, v, tun.chains_per_block);
     }
-    sort_tasks_longest_first(tasks, lens);
+    if (tun.order == 0) sort_tasks_longest_first(tasks, lens);
     int rc = plan_upload_tables(*p, views, tasks);
     if (rc) {
         sf_plan_destroy(reinterpret_cast<sf_plan>(p));
         return rc;
     }
-    p->persistent_blocks = (flags & SF_FRAME_PERSISTENT) ? default_persistent_blocks() : 0;
+    p->tuning = tun;
+    p->persistent_blocks = tun.persistent_per_cu > 0 ? tun.persistent_per_cu * cu_count_dev() : 0;
     *out = reinterpret_cast<sf_plan>(p);
     return SF_OK;
 }
@@ -178,7 +190,8 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     if (rc) return rc;
 
     rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
-                          p->persistent_blocks, st);
+                          p->persistent_blocks, st,
+                          p->tuning.chains_per_block, p->tuning.prefetch);
     if (rc) return rc;
 
     int16_t *wtar[2], *wtal[2];
@@ -260,7 +273,8 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     co.n = 2; co.H = H; co.W = W; co.D = D;
     if ((rc = launch_cost(co, st))) return rc;
     if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
-                               p->persistent_blocks, st)))
+                               p->persistent_blocks, st,
+                          p->tuning.chains_per_block, p->tuning.prefetch)))
         return rc;
     // WTA + sub-pixel + features of both left maps (no right view).
     float *feat = reinterpret_cast<float *>(at(p->off_feat));

@@ -29,11 +29,12 @@ struct Plan {
     int *d_counter = nullptr;
     int ntasks = 0, nviews = 0;
     int persistent_blocks = 0;
+    sf_agg_tuning tuning{16, 8, 0, 0};
     // Batch plans: pairs, waves, per-class tunings, captured graph.
     BatchData *batch = nullptr;
 };
 
 int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::vector<AggTask> &tasks);
-int default_persistent_blocks();
+int cu_count_dev();
 
 }  // namespace sf

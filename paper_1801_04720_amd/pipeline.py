@@ -58,13 +58,13 @@ class FusedFrame:
 
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
                  cam=(721.5, 0.54, None, None), persistent: bool = False, learned_params=None,
-                 device="cuda:0"):
+                 tuning=None, device="cuda:0"):
         self.H, self.W, self.D = H, W, D
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
         self.params = learned_params
         self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent,
-                                   learned=learned_params is not None)
+                                   learned=learned_params is not None, tuning=tuning)
         dev = torch.device(device)
         e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
         self.ws = e(self.plan.workspace_bytes(), dt=torch.uint8)
