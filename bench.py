@@ -185,6 +185,83 @@ def bench_batch(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def _gen_frame(i):
+    from paper_1801_04720_amd import synth
+
+    fr = synth.frame_planar(synth.rng_for(5, i), 1024, 2048, 256, 200.0)
+    return fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right, fr.flow
+
+
+def bench_stream(args, dev):
+    """Stream of 2048x1024 D=256 frames resident in HBM: the learned frame on every
+    frame (t0 and t1 aggregated in one launch), the plain frame as judge on every
+    16th; per-frame latency from events on the stream; compared with the all-plain
+    stream on the same frames."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import batch
+    from paper_1801_04720_amd.pipeline import FusedFrame
+
+    H, W, D = 1024, 2048, 256
+    n = args.frames
+    with cf.ProcessPoolExecutor(max_workers=14) as ex:
+        frames = [tuple(torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in f)
+                  for f in ex.map(_gen_frame, range(n), chunksize=2)]
+    with np.load(args.lrnet, allow_pickle=False) as z:
+        prm = torch.from_numpy(z["params"].astype(np.float32)).to(dev)
+    t2, _ = batch.autotune(H, W, D, nviews=2, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+    t4, _ = batch.autotune(H, W, D, nviews=4, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+    learned = FusedFrame(H, W, D, learned_params=prm, tuning=t2, device=dev)
+    plain = FusedFrame(H, W, D, tuning=t4, device=dev)
+    s = torch.cuda.current_stream()
+
+    def run_stream(judge_every):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+        agree = []
+        for i, f in enumerate(frames[:2]):  # warm-up
+            (learned if judge_every else plain).run(*f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, f in enumerate(frames):
+            ev[i][0].record(s)
+            if judge_every:
+                out = learned.run(*f)
+                if i % judge_every == 0:
+                    ref = plain.run(*f)
+                    agree.append([float((out[k] == ref[k]).float().mean().item()) for k in ("valid0", "valid1")])
+            else:
+                plain.run(*f)
+            ev[i][1].record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([a.elapsed_time(b) for a, b in ev])
+        return wall, lat, agree
+
+    wl, ll, agree = run_stream(16)
+    wp, lp, _ = run_stream(0)
+    res = {
+        "metric": "scene-flow stream: sustained fps + p50/p99 per-frame latency @2048x1024 D=256",
+        "value": n / wl, "unit": "frames/s", "n_gpus": 1, "steps": n, "warmup": 2,
+        "ms_per_step": 1e3 * wl / n, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u16", "data": "synthetic (seeded piecewise-planar 2048x1024 frames, flow within 200 px)",
+        "config": {"workload": f"{n} frames 2048x1024 D=256: learned frame (t0+t1 in one aggregation "
+                               "launch, network mask) with the plain frame as judge on every 16th"},
+        "learned_stream": {"fps": n / wl, "p50_ms": float(np.percentile(ll, 50)),
+                           "p99_ms": float(np.percentile(ll, 99))},
+        "plain_stream": {"fps": n / wp, "p50_ms": float(np.percentile(lp, 50)),
+                         "p99_ms": float(np.percentile(lp, 99))},
+        "speedup_learned_vs_plain": wp / wl,
+        "judge_mask_agreement_mean": [float(np.mean([a[0] for a in agree])), float(np.mean([a[1] for a in agree]))],
+        "judge_mask_agreement_min": [float(np.min([a[0] for a in agree])), float(np.min([a[1] for a in agree]))],
+        "judged_frames": len(agree),
+        "tuning": {"learned_2views": batch.tuning_dict(t2), "plain_4views": batch.tuning_dict(t4)},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     """Learned frame (right views skipped, network mask): fps, speed-up over the
     plain frame, and agreement of its masks with the plain LR check on this frame."""
@@ -243,9 +320,11 @@ def main():
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
                                                     "lrnet_c2.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
                     help="c2: the 1242x375 D=128 scene-flow frame (default); c3: the uneven "
-                         "batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256)")
+                         "batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); c5: a "
+                         "stream of 2048x1024 D=256 frames, learned with a plain judge every 16th")
+    ap.add_argument("--frames", type=int, default=240, help="frames in the c5 stream")
     ap.add_argument("--pairs", type=int, default=64, help="pairs in the c3 batch")
     ap.add_argument("--mem-budget-gb", type=float, default=128.0, help="c3 workspace per wave")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -278,6 +357,8 @@ def main():
     lib = _lib.lib()
     if args.workload == "c3":
         return bench_batch(args, dev)
+    if args.workload == "c5":
+        return bench_stream(args, dev)
     H, W, D = 375, 1242, 128
     fr = synth.frame_c2(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
