@@ -2,6 +2,7 @@
 entry point (all four aggregations in one launch, slabs summed inside WTA),
 its persistent variant, and the per-stage path, at a small size and at the
 full 1242x375 / D=128 size."""
+import os
 import sys
 
 import numpy as np
@@ -124,3 +125,87 @@ def test_learned_frame_equals_stagewise(orc):
     assert np.array_equal(host(maps[0][2]), w0)
     xs = np.arange(W)[None, :]
     assert not (got["valid0"].astype(bool) & ((xs - w0) < 0)).any()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 50), (50, 1), (7, 9)])
+def test_fused_frame_degenerate_shapes(orc, H, W):
+    say("fused frame degenerate", H, W)
+    D = 32
+    rng = np.random.default_rng(H * 100 + W)
+    imgs = [rng.integers(0, 256, (H, W)).astype(np.uint8) for _ in range(4)]
+    flow = rng.normal(0, 2, (H, W, 2)).astype(np.float32)
+
+    class F:
+        pass
+
+    fr = F()
+    fr.t0, fr.t1 = F(), F()
+    fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right = imgs
+    fr.flow = flow
+    ff = FusedFrame(H, W, D, device=DEV)
+    got = ff.run(dev(imgs[0]), dev(imgs[1]), dev(imgs[2]), dev(imgs[3]), dev(flow))
+    torch.cuda.synchronize()
+    check_frame(got, oracle_frame(orc, fr, D, ff.cam))
+
+
+def test_fused_frame_max_size_vs_stagewise():
+    """2048x1024, D = 256 (the largest workload): fused frame == per-stage path."""
+    say("fused frame 2048x1024 D=256 vs per-stage")
+    fr = synth.frame_planar(synth.rng_for(5, 0), 1024, 2048, 256, 200.0)
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    a = FusedFrame(1024, 2048, 256, device=DEV).run(*args)
+    a = {k: host(v).copy() for k, v in a.items()}
+    m0, m1, c = PlainFrame(1024, 2048, 256, device=DEV).run(*args)
+    torch.cuda.synchronize()
+    assert np.array_equal(a["valid0"], host(m0["valid"]))
+    assert np.array_equal(a["disp0"], host(m0["disp"]))
+    assert np.array_equal(a["valid1"], host(m1["valid"]))
+    for k in ("sf4", "valid", "xyz0", "motion"):
+        assert np.array_equal(a[k], host(c[k]), equal_nan=True), k
+
+
+@pytest.mark.parametrize("idx", [0, 1, 2, 3])
+def test_gpu_exact_recovery_piecewise_constant(idx):
+    """On the 320x96 D=32 piecewise-constant pairs the GPU path recovers the ground
+    truth on the clean interior (the property the oracle is pinned to)."""
+    from test_oracle_sgm import clean_interior
+    from paper_1801_04720_amd import api
+
+    say("gpu exact recovery", idx)
+    p = synth.pair_c1(idx)
+    L, R = dev(p.left), dev(p.right)
+    cl, cr = api.census(L), api.census(R)
+    Sr = api.sgm_aggregate(api.cost(cr, cl, 32, True), 10, 120)
+    Sl = api.sgm_aggregate(api.cost(cl, cr, 32, False), 10, 120)
+    out = api.wta_lr(Sl, Sr, None, 120, 1)
+    ok = clean_interior(p)
+    assert np.array_equal(host(out["wta_left"])[ok], p.gt_disp[ok].astype(np.int16))
+    assert host(out["valid"])[ok].all()
+
+
+def test_learned_frame_network_vs_oracle_c2(orc):
+    """Full-size learned frame: features and logits of the t0 map against the
+    oracle's (features bit-exact; logits within BF16 rounding effects; the masks
+    agree wherever the oracle's logit is not within 0.05 of zero)."""
+    from paper_1801_04720_amd import api, lrnet
+
+    say("learned network vs oracle at 1242x375")
+    fr = synth.frame_c2(2)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with np.load(os.path.join(root, "paper_1801_04720_amd", "data", "lrnet_c2.npz"), allow_pickle=False) as z:
+        prm = z["params"].astype(np.float32)
+    L, R = dev(fr.t0.left), dev(fr.t0.right)
+    cl, cr = api.census(L), api.census(R)
+    Sl = api.sgm_aggregate(api.cost(cl, cr, 128, False), 10, 120)
+    m = api.wta_lr(Sl, None, L, 120, 1, want_feat=True)
+    logits = host(lrnet.forward(dev(prm), m["feat"][None].contiguous()))[0]
+    S = orc.aggregate(orc.cost(orc.census(fr.t0.left), orc.census(fr.t0.right), 128, False), 10, 120)
+    w, _ = orc.wta(S)
+    feat = orc.features(fr.t0.left, S, w, 120)
+    assert np.array_equal(host(m["feat"]), feat)
+    _, ref, _ = orc.lrnet(feat, prm)
+    ref = ref[0]
+    err = np.abs(logits - ref)
+    assert np.quantile(err, 0.999) <= 0.05 * (1 + np.abs(ref)).max()
+    far = np.abs(ref) > 0.05
+    assert np.array_equal(logits[far] > 0, ref[far] > 0)
