@@ -88,15 +88,12 @@ __global__ __launch_bounds__(COST_NT) void cost_kernel(CostArgs a)
         if (xm < 0 || xm >= W) return SF_CMAX;
         return (uint32_t)__popcll(sb[p] ^ sm[xm - mlo]);
     };
-    if ((D & 3) == 0) {
+    if (a.vec == 4) {
         const int qpp = D >> 2;  // 32-bit words per pixel
         const int nw = np * qpp;
         uint32_t *o32 = reinterpret_cast<uint32_t *>(out);
-        // Power-of-two words per pixel (D = 32, 64, 128, 256): shifts, no division.
-        const bool pow2 = (qpp & (qpp - 1)) == 0;
-        const int sh = __ffs(qpp) - 1;
         for (int j = threadIdx.x; j < nw; j += COST_NT) {
-            const int p = pow2 ? (j >> sh) : j / qpp;
+            const int p = j / qpp;
             const int d = (j - p * qpp) * 4;
             uint32_t w = one(p, d) | (one(p, d + 1) << 8) | (one(p, d + 2) << 16) |
                          (one(p, d + 3) << 24);
@@ -111,6 +108,113 @@ __global__ __launch_bounds__(COST_NT) void cost_kernel(CostArgs a)
     }
 }
 
+// 16-byte path (D a multiple of 16, aligned output).  Thread (chunk c, run j)
+// produces disparities [16c, 16c + 16) of CV_R consecutive pixels; the
+// CV_R + 15 match census words it needs are read once from LDS into registers
+// (a sliding window) instead of once per disparity.  The chunk index runs
+// fastest, so the threads of one pixel write its D bytes contiguously.
+// LDS index i is stored at i + i/8: a wave's reads hit indices 8k + const,
+// which this maps to distinct banks.
+constexpr int CV_NT = 256;  // threads per block
+constexpr int CV_R = 8;     // consecutive pixels per thread
+
+__host__ __device__ __forceinline__ int cv_swz(int i) { return i + (i >> 3); }
+
+__device__ __forceinline__ uint32_t hamming(uint64_t b, uint64_t m)
+{
+    const uint64_t x = b ^ m;
+    return (uint32_t)__popc((uint32_t)x) + (uint32_t)__popc((uint32_t)(x >> 32));
+}
+
+template <bool RIGHT, bool EDGE>
+__device__ __forceinline__ void cost_run16(const uint64_t *sb, const uint64_t *sm, int j, int c,
+                                           int x0, int W, int D, uint8_t *row)
+{
+    // Window word k holds the match census at LDS index  j R + 16c + k (right
+    // base; element (r, e) uses k = r + e) or  j R + D - 1 - 16c - 15 + k
+    // (left base; element (r, e) uses k = r - e + 15).
+    uint64_t win[CV_R + 15];
+    const int w0 = RIGHT ? j * CV_R + 16 * c : j * CV_R + D - 16 - 16 * c;
+#pragma unroll
+    for (int k = 0; k < CV_R + 15; ++k) win[k] = sm[cv_swz(w0 + k)];
+#pragma unroll
+    for (int r = 0; r < CV_R; ++r) {
+        const int xl = j * CV_R + r;  // block-local pixel
+        const int x = x0 + xl;
+        const uint64_t b = sb[cv_swz(xl)];
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int e = 4 * q + e4;
+                uint32_t v = hamming(b, win[RIGHT ? r + e : r - e + 15]);
+                if (EDGE) {
+                    const int d = 16 * c + e;
+                    const bool out = RIGHT ? (x + d >= W) : (x - d < 0);
+                    v = out ? (uint32_t)SF_CMAX : v;
+                }
+                acc = e4 == 0 ? v : (acc | (v << (8 * e4)));
+            }
+            w[q] = acc;
+        }
+        if (x < W) reinterpret_cast<uint4 *>(row + (size_t)xl * D)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+__global__ __launch_bounds__(CV_NT) void cost16_kernel(CostArgs a)
+{
+    extern __shared__ uint64_t cv_lds[];
+    const int H = a.H, W = a.W, D = a.D;
+    (void)H;
+    const uint64_t *__restrict__ cb = a.base[blockIdx.z];
+    const uint64_t *__restrict__ cm = a.match[blockIdx.z];
+    const bool RIGHT = a.right[blockIdx.z] != 0;
+    const int cpp = D >> 4;           // 16-disparity chunks per pixel
+    const int runs = CV_NT / cpp;     // pixel runs per block
+    const int TP = runs * CV_R;       // pixels per block
+    const int y = blockIdx.y, x0 = blockIdx.x * TP;
+    const int mn = TP + D - 1;        // match words: x0 - D + 1 .. x0 + TP - 1 (left), x0 .. x0 + TP + D - 2 (right)
+    const int mlo = RIGHT ? x0 : x0 - D + 1;
+    uint64_t *sb = cv_lds;
+    uint64_t *sm = cv_lds + cv_swz(TP - 1) + 1;
+    const uint64_t *rb = cb + (size_t)y * W;
+    const uint64_t *rm = cm + (size_t)y * W;
+    for (int i = threadIdx.x; i < TP; i += CV_NT) {
+        const int gx = x0 + i;
+        sb[cv_swz(i)] = gx < W ? rb[gx] : 0;
+    }
+    for (int i = threadIdx.x; i < mn; i += CV_NT) {
+        const int gx = mlo + i;
+        sm[cv_swz(i)] = (gx >= 0 && gx < W) ? rm[gx] : 0;
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int c = t % cpp, j = t / cpp;
+    if (j >= runs) return;
+    uint8_t *row = a.cost[blockIdx.z] + ((size_t)y * W + x0) * D;
+    if (RIGHT) {
+        if (x0 + TP + D - 2 >= W)
+            cost_run16<true, true>(sb, sm, j, c, x0, W, D, row);
+        else
+            cost_run16<true, false>(sb, sm, j, c, x0, W, D, row);
+    } else {
+        if (x0 < D - 1)
+            cost_run16<false, true>(sb, sm, j, c, x0, W, D, row);
+        else
+            cost_run16<false, false>(sb, sm, j, c, x0, W, D, row);
+    }
+}
+
+// Pixels per block and dynamic LDS bytes of cost16_kernel.
+static inline int cv_tile(int D) { return (CV_NT / (D >> 4)) * CV_R; }
+static inline size_t cv_lds_bytes(int D)
+{
+    const int TP = cv_tile(D);
+    return (size_t)(cv_swz(TP - 1) + 1 + cv_swz(TP + D - 2) + 1) * sizeof(uint64_t);
+}
+
 int launch_census(const CensusArgs &a, hipStream_t st)
 {
     dim3 grid((a.W + CEN_TW - 1) / CEN_TW, (a.H + CEN_TH - 1) / CEN_TH, a.n);
@@ -119,10 +223,20 @@ int launch_census(const CensusArgs &a, hipStream_t st)
     return launch_status("census_kernel");
 }
 
-int launch_cost(const CostArgs &a, hipStream_t st)
+int launch_cost(const CostArgs &args, hipStream_t st)
 {
-    dim3 grid((a.W + COST_TP - 1) / COST_TP, a.H, a.n);
+    CostArgs a = args;
+    uintptr_t ptr_bits = 0;
+    for (int i = 0; i < a.n; ++i) ptr_bits |= reinterpret_cast<uintptr_t>(a.cost[i]);
+    a.vec = ((a.D & 15) == 0 && (ptr_bits & 15) == 0) ? 16 : ((a.D & 3) == 0 && (ptr_bits & 3) == 0) ? 4 : 1;
     ProfScope prof("cost", st);
+    if (a.vec == 16) {
+        const int TP = cv_tile(a.D);
+        dim3 grid((a.W + TP - 1) / TP, a.H, a.n);
+        hipLaunchKernelGGL(cost16_kernel, grid, dim3(CV_NT), cv_lds_bytes(a.D), st, a);
+        return launch_status("cost16_kernel");
+    }
+    dim3 grid((a.W + COST_TP - 1) / COST_TP, a.H, a.n);
     hipLaunchKernelGGL(cost_kernel, grid, dim3(COST_NT), 0, st, a);
     return launch_status("cost_kernel");
 }

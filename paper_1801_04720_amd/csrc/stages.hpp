@@ -25,6 +25,7 @@ struct CostArgs {
     uint8_t *cost[STAGE_MAXV];
     int right[STAGE_MAXV];
     int n, H, W, D;
+    int vec;  // store width in bytes (16, 4 or 1), set by launch_cost from D and the pointers' alignment
 };
 
 // WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8).

@@ -48,7 +48,7 @@ def test_census_pitch(orc):
 
 # --- cost -----------------------------------------------------------------------------
 
-@pytest.mark.parametrize("D", [1, 3, 5, 32, 100, 128, 256])
+@pytest.mark.parametrize("D", [1, 3, 5, 16, 32, 48, 96, 100, 128, 256])
 @pytest.mark.parametrize("right", [False, True])
 def test_cost(orc, D, right):
     say("cost", D, right)
@@ -57,6 +57,23 @@ def test_cost(orc, D, right):
     base, match = (cr, cl) if right else (cl, cr)
     got = host(api.cost(dev(base), dev(match), D, right))
     assert np.array_equal(got, orc.cost(base, match, D, right))
+
+
+@pytest.mark.parametrize("offset", [1, 4, 8])
+def test_cost_unaligned_output(orc, offset):
+    """Output pointers that are not 16-byte aligned take the narrower stores."""
+    say("cost unaligned", offset)
+    p = synth.pair_c1(2)
+    cl, cr = orc.census(p.left), orc.census(p.right)
+    H, W, D = p.left.shape[0], p.left.shape[1], 32
+    buf = torch.full((H * W * D + 16,), 255, dtype=torch.uint8, device=DEV)
+    tl, tr = dev(cl), dev(cr)
+    _lib.check(_lib.lib().sf_cost(ct.c_void_p(tl.data_ptr()), ct.c_void_p(tr.data_ptr()), H, W, D, 0,
+                                  ct.c_void_p(buf.data_ptr() + offset),
+                                  ct.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    got = host(buf)
+    assert np.array_equal(got[offset:offset + H * W * D].reshape(H, W, D), orc.cost(cl, cr, D, False))
+    assert (got[:offset] == 255).all() and (got[offset + H * W * D:] == 255).all()
 
 
 # --- aggregation ------------------------------------------------------------------------
