@@ -130,6 +130,22 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
     uint32_t sv[2][4];
     int dd[2][8];
     uint32_t best = 0xFFFFFFFFu;
+    // All slab loads of the lane are issued before any is used (slabs past
+    // nslab re-read the last one and are masked to zero), so each wave keeps
+    // up to 16 loads in flight.
+    const int ns = v.nslab;
+    u32x2 w[2][8];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int c = j + 16 * i;
+        if (8 * c < D) {
+            const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                w[i][k] = __builtin_nontemporal_load(
+                    reinterpret_cast<const u32x2 *>(src + (size_t)min(k, ns - 1) * cells));
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
@@ -138,14 +154,14 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 #pragma unroll
         for (int e = 0; e < 8; ++e) dd[i][e] = slab_pos_to_d<K>(8 * c + e);
         if (8 * c < D) {
-            const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
-            for (int k = 0; k < v.nslab; ++k) {
-                const u32x2 w = __builtin_nontemporal_load(
-                    reinterpret_cast<const u32x2 *>(src + (size_t)k * cells));
-                sv[i][0] += __builtin_amdgcn_perm(0u, w.x, 0x0c010c00u);
-                sv[i][1] += __builtin_amdgcn_perm(0u, w.x, 0x0c030c02u);
-                sv[i][2] += __builtin_amdgcn_perm(0u, w.y, 0x0c010c00u);
-                sv[i][3] += __builtin_amdgcn_perm(0u, w.y, 0x0c030c02u);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t keep = k < ns ? 0xFFFFFFFFu : 0u;
+                const uint32_t lo = w[i][k].x & keep, hi = w[i][k].y & keep;
+                sv[i][0] += __builtin_amdgcn_perm(0u, lo, 0x0c010c00u);
+                sv[i][1] += __builtin_amdgcn_perm(0u, lo, 0x0c030c02u);
+                sv[i][2] += __builtin_amdgcn_perm(0u, hi, 0x0c010c00u);
+                sv[i][3] += __builtin_amdgcn_perm(0u, hi, 0x0c030c02u);
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -221,8 +237,10 @@ int launch_wta_slabs(WtaArgs &a, hipStream_t st)
     for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
     if (tot <= 0) return SF_OK;
     if (tot > 0x7FFFFFFFLL) return fail(SF_EINVAL, "launch_wta_slabs: grid too large");
-    for (int i = 1; i < a.n; ++i)
+    for (int i = 0; i < a.n; ++i) {
         if (a.v[i].D != a.v[0].D) return fail(SF_EINVAL, "launch_wta_slabs: views of one launch need one D");
+        if (a.v[i].nslab < 1 || a.v[i].nslab > 8) return fail(SF_EINVAL, "launch_wta_slabs: nslab must be in [1, 8]");
+    }
     ProfScope prof(a.v[0].right_only ? "wta_slab_right" : "wta_slab_left", st);
     switch (a.v[0].D / 16) {
 #define SF_WTA_CASE(KK)                                                                             \
