@@ -12,6 +12,7 @@ Prints one JSON line.  `value` is GCUPS per delivered disparity map
 from __future__ import annotations
 
 import argparse
+import ctypes as ct
 import json
 import os
 import sys
@@ -304,6 +305,47 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
             "sceneflow_density_learned": both(out["valid"])}
 
 
+def bench_peaks(args, dev):
+    """Measured ceilings: HBM stream rates (2 GiB buffers, far above the 256 MB
+    last-level cache), the same copy on a 64 MiB buffer that the last-level cache
+    holds, and the packed 16-bit VALU rate."""
+    import torch
+    from paper_1801_04720_amd import _lib
+
+    lib = _lib.lib()
+    st = torch.cuda.current_stream()
+    sp = ct.c_void_p(st.cuda_stream)
+    reps = max(args.steps, 3)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"metric": "measured ceilings", "reps": reps}
+    for label, nbytes in (("hbm", 2 << 30), ("llc", 64 << 20)):
+        a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        pa, pb = ct.c_void_p(a.data_ptr()), ct.c_void_p(b.data_ptr())
+        for mode, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "write", nbytes)):
+            ms = timed(lambda: _lib.check(lib.sf_probe_stream(pa, pb, nbytes, mode, sp)))
+            out[f"{label}_{name}_GBps"] = moved / (ms * 1e-3) / 1e9
+        del a, b
+    props = torch.cuda.get_device_properties(0)
+    blocks, iters = props.multi_processor_count * 32, 8192
+    o = torch.empty(blocks * 256, dtype=torch.int32, device=dev)
+    ms = timed(lambda: _lib.check(lib.sf_probe_pk_u16(ct.c_void_p(o.data_ptr()), blocks, iters, sp)))
+    out["valu_pk_u16_Tops"] = blocks * 256 * iters * 32 / (ms * 1e-3) / 1e12
+    out["cu"] = props.multi_processor_count
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +369,9 @@ def main():
     ap.add_argument("--frames", type=int, default=240, help="frames in the c5 stream")
     ap.add_argument("--pairs", type=int, default=64, help="pairs in the c3 batch")
     ap.add_argument("--mem-budget-gb", type=float, default=128.0, help="c3 workspace per wave")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure the HBM / last-level-cache stream rates and the packed "
+                         "16-bit VALU rate, and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference kernel "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -344,6 +389,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
+    if args.peaks:
+        return bench_peaks(args, dev)
     if args.copy_calibration:
         n = 1 << 30
         a = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -412,6 +459,11 @@ def main():
                 "frac": achieved / PEAK_U16_TOPS, "traffic": measured_traffic(kname),
                 "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"],
                 "gcups_per_launch": cells * views_per_launch / avg_s / 1e9}
+    if roofline["traffic"]:
+        # The launch's HBM-side bytes per second against the 8 TB/s HBM peak: the
+        # aggregation is bound by this traffic, not by its packed 16-bit ALU work.
+        roofline["traffic_TBps"] = roofline["traffic"] / avg_s / 1e12
+        roofline["traffic_frac_of_hbm_peak"] = roofline["traffic_TBps"] / 8.0
     if args.pipeline == "stages":
         m0, m1, out = res_run
         v0t, vt = m0["valid"], out["valid"]

@@ -293,6 +293,23 @@ int sf_prof_enable(int max_launches);
 int sf_prof_disable(void);
 int sf_prof_query(const char *kernel, double *total_ms, int *launches);
 
+/* ---------------------------------------------------------------------------
+ * Machine-balance probes (not part of the method): the measured ceilings the
+ * kernels' roofline fractions are also quoted against.
+ *
+ * sf_probe_stream: mode 0 copies `bytes` from src to dst, mode 1 only reads
+ * src, mode 2 only writes dst (16-byte non-temporal accesses).  bytes a
+ * multiple of 16, pointers 16-byte aligned device memory (dst unused in mode 1,
+ * src unused in mode 2).  Errors: SF_EINVAL, SF_EHIP.
+ *
+ * sf_probe_pk_u16: `blocks` blocks of 256 threads; each thread runs `iters`
+ * iterations of 8 packed 16-bit adds and 8 packed 16-bit mins (the
+ * instruction mix of the path-cost recurrence), i.e. blocks*256*iters*32
+ * 16-bit element operations, and writes a checksum to out[blocks*256]
+ * (uint32, device).  Errors: SF_EINVAL, SF_EHIP. */
+int sf_probe_stream(const void *src, void *dst, size_t bytes, int mode, void *stream);
+int sf_probe_pk_u16(uint32_t *out, int blocks, int iters, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,8 @@ SIGNATURES = {
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),
+    "sf_probe_stream": (I, [P, P, SZ, I, P]),
+    "sf_probe_pk_u16": (I, [P, I, I, P]),
 }
 
 _lib = None
