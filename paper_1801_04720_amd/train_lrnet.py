@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import concurrent.futures as cf
 import json
+import os
 import time
 
 import numpy as np
@@ -68,6 +69,9 @@ def evaluate(params, feats, labels, wtas, dsubs, gts, occs, dev="cuda:0"):
     agree = 0.0
     tp = fp = fn = tn = 0
     epe_l, epe_p, den_l, den_p = [], [], [], []
+    # Baselines without a learned or LR mask: keep every pixel ("no check"), or
+    # drop only those whose match falls outside the right image (x - d* < 0).
+    epe_n, den_n, epe_g, den_g, agree_g = [], [], [], [], 0.0
     for k in range(n):
         logits = lrnet.forward(params, feats[k:k + 1])
         learned = (logits[0] > 0) & ((xs[0] - wtas[k].long()) >= 0)
@@ -79,13 +83,20 @@ def evaluate(params, feats, labels, wtas, dsubs, gts, occs, dev="cuda:0"):
         fn += int((~learned & lab).sum())
         gt = torch.from_numpy(gts[k]).to(dev)
         err = (dsubs[k] - gt).abs()
-        for m, e, d in ((learned, epe_l, den_l), (lab, epe_p, den_p)):
+        geom = (xs[0] - wtas[k].long()) >= 0
+        nocheck = torch.ones_like(lab)
+        agree_g += float((geom == lab).float().mean().item())
+        for m, e, d in ((learned, epe_l, den_l), (lab, epe_p, den_p), (nocheck, epe_n, den_n),
+                        (geom, epe_g, den_g)):
             e.append(float(err[m].mean().item()))
             d.append(float(m.float().mean().item()))
     return {"agreement": agree / n, "tp": tp, "tn": tn, "fp": fp, "fn": fn,
             "epe_learned_mask": float(np.mean(epe_l)), "epe_lr_mask": float(np.mean(epe_p)),
             "density_learned": float(np.mean(den_l)), "density_lr": float(np.mean(den_p)),
-            "agreement_no_check": float(sum(float(labels[k].float().mean()) for k in range(n)) / n)}
+            "agreement_no_check": float(sum(float(labels[k].float().mean()) for k in range(n)) / n),
+            "epe_no_check": float(np.mean(epe_n)), "density_no_check": float(np.mean(den_n)),
+            "agreement_geometric": agree_g / n, "epe_geometric_mask": float(np.mean(epe_g)),
+            "density_geometric": float(np.mean(den_g))}
 
 
 def main():
@@ -99,8 +110,29 @@ def main():
     ap.add_argument("--workers", type=int, default=12)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="lrnet.npz")
+    ap.add_argument("--eval-only", default=None,
+                    help="evaluate the parameters of this .npz on the validation pairs and exit")
+    ap.add_argument("--metrics-out", default=None,
+                    help="with --eval-only: merge the metrics into this JSON file")
     args = ap.parse_args()
     dev = "cuda:0"
+    if args.eval_only:
+        with np.load(args.eval_only, allow_pickle=False) as z:
+            params = torch.from_numpy(z["params"].astype(np.float32)).to(dev)
+        vf, vl, vw, vd, vg, vo = label_pairs(list(range(100000, 100000 + args.val)), args.workers,
+                                              dev, keep_gt=True)
+        ev = evaluate(params, vf, vl, vw, vd, vg, vo, dev)
+        ev["val_pairs"] = args.val
+        print(json.dumps(ev), flush=True)
+        if args.metrics_out:
+            old = {}
+            if os.path.exists(args.metrics_out):
+                with open(args.metrics_out) as f:
+                    old = json.load(f)
+            old.update(ev)
+            with open(args.metrics_out, "w") as f:
+                json.dump(old, f, indent=1)
+        return
     t0 = time.time()
     feats, labels, _, _, _, _ = label_pairs(list(range(args.pairs)), args.workers, dev)
     vf, vl, vw, vd, vg, vo = label_pairs(list(range(100000, 100000 + args.val)), args.workers, dev,
