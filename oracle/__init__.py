@@ -56,6 +56,11 @@ def _declare(L):
     L.oracle_no_check.argtypes = [P, I, I, P, P]
     L.oracle_combine.argtypes = [P, P, P, P, P, I, I, I, F, F, F, F, P, P, P, P]
     L.oracle_disparity.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, P, P, P]
+    L.oracle_path_cost_adaptive.argtypes = [P, P, I, I, I, I, I, I, I, P]
+    L.oracle_aggregate_adaptive.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, P]
+    L.oracle_wta_right_diag.argtypes = [P, I, I, I, P]
+    L.oracle_median3x3.argtypes = [P, I, I, P]
+    L.oracle_disparity_ex.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P, P, P]
     L.oracle_features.argtypes = [P, I, P, P, I, I, I, I, P]
     L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
     L.oracle_lrnet.restype = ct.c_double
@@ -100,6 +105,44 @@ def aggregate(cost_vol: np.ndarray, P1: int, P2: int, path_mask: int = 0xFF) -> 
     H, W, D = c.shape
     out = np.zeros((H, W, D), np.uint16)
     lib().oracle_aggregate(_p(c), H, W, D, P1, P2, path_mask, _p(out))
+    return out
+
+
+def path_cost_adaptive(cost_vol: np.ndarray, img: np.ndarray, P1: int, P2: int,
+                       direction: int) -> np.ndarray:
+    """Path cost with the intensity-adaptive large-jump penalty (img = base image)."""
+    c = np.ascontiguousarray(cost_vol, np.uint8)
+    im = np.ascontiguousarray(img, np.uint8)
+    H, W, D = c.shape
+    out = np.zeros((H, W, D), np.int32)
+    lib().oracle_path_cost_adaptive(_p(c), _p(im), W, H, W, D, P1, P2, direction, _p(out))
+    return out
+
+
+def aggregate_adaptive(cost_vol: np.ndarray, img: np.ndarray, P1: int, P2: int,
+                       path_mask: int = 0xFF) -> np.ndarray:
+    c = np.ascontiguousarray(cost_vol, np.uint8)
+    im = np.ascontiguousarray(img, np.uint8)
+    H, W, D = c.shape
+    out = np.zeros((H, W, D), np.uint16)
+    lib().oracle_aggregate_adaptive(_p(c), _p(im), W, H, W, D, P1, P2, path_mask, _p(out))
+    return out
+
+
+def wta_right_diag(S: np.ndarray) -> np.ndarray:
+    """Right-view WTA by the diagonal search in the left volume S_L."""
+    S = np.ascontiguousarray(S, np.uint16)
+    H, W, D = S.shape
+    w = np.zeros((H, W), np.int16)
+    lib().oracle_wta_right_diag(_p(S), H, W, D, _p(w))
+    return w
+
+
+def median3x3(m: np.ndarray) -> np.ndarray:
+    m = np.ascontiguousarray(m, np.float32)
+    H, W = m.shape
+    out = np.zeros((H, W), np.float32)
+    lib().oracle_median3x3(_p(m), H, W, _p(out))
     return out
 
 
@@ -165,6 +208,22 @@ def disparity(left, right, D, P1=10, P2=120, path_mask=0xFF, tol=1):
     valid = np.zeros((H, W), np.uint8)
     lib().oracle_disparity(_p(L), _p(R), H, W, W, D, P1, P2, path_mask, tol, _p(w), _p(disp),
                            _p(valid))
+    return w, disp, valid
+
+
+DIAG, MEDIAN, ADAPTIVE = 1, 2, 4
+
+
+def disparity_ex(left, right, D, flags, P1=10, P2=120, path_mask=0xFF, tol=1):
+    """Disparity map of one pair with the SGM variants (DIAG | MEDIAN | ADAPTIVE)."""
+    L = np.ascontiguousarray(left, np.uint8)
+    R = np.ascontiguousarray(right, np.uint8)
+    H, W = L.shape
+    w = np.zeros((H, W), np.int16)
+    disp = np.zeros((H, W), np.float32)
+    valid = np.zeros((H, W), np.uint8)
+    lib().oracle_disparity_ex(_p(L), _p(R), H, W, W, D, P1, P2, path_mask, tol, flags, _p(w),
+                              _p(disp), _p(valid))
     return w, disp, valid
 
 

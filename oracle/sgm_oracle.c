@@ -105,8 +105,20 @@ static const int ORACLE_DIR[8][2] = {
     {+1, 0}, {-1, 0}, {0, +1}, {0, -1}, {+1, +1}, {-1, +1}, {+1, -1}, {-1, -1}};
 
 /* One direction's path cost volume, Lr[(y * W + x) * D + d]. */
-void oracle_path_cost(const uint8_t *cost, int H, int W, int D, int P1, int P2, int dir,
-                      int32_t *Lr)
+/* Path cost of one direction with the large-jump penalty taken per pixel:
+ * p2map == NULL gives the constant P2; otherwise the penalty at p is
+ * p2map(p, p - r) (see oracle_path_cost_adaptive). */
+static int adaptive_p2(const uint8_t *img, int pitch, int x, int y, int px, int py, int P1, int P2)
+{
+    int g = (int)img[(size_t)y * pitch + x] - (int)img[(size_t)py * pitch + px];
+    if (g < 0) g = -g;
+    if (g == 0) return P2;
+    int q = P2 / g;
+    return q > P1 ? q : P1;
+}
+
+static void path_cost(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W, int D,
+                      int P1, int P2, int dir, int32_t *Lr)
 {
     int rx = ORACLE_DIR[dir][0], ry = ORACLE_DIR[dir][1];
     /* Visit pixels so that p - r is always visited before p. */
@@ -121,6 +133,7 @@ void oracle_path_cost(const uint8_t *cost, int H, int W, int D, int P1, int P2, 
                 for (int d = 0; d < D; ++d) L[d] = C[d];
                 continue;
             }
+            const int p2 = img ? adaptive_p2(img, pitch, x, y, px, py, P1, P2) : P2;
             const int32_t *Lp = Lr + ((size_t)py * W + px) * D;
             int32_t M = Lp[0];
             for (int k = 1; k < D; ++k)
@@ -129,27 +142,57 @@ void oracle_path_cost(const uint8_t *cost, int H, int W, int D, int P1, int P2, 
                 int32_t best = Lp[d];
                 if (d - 1 >= 0 && Lp[d - 1] + P1 < best) best = Lp[d - 1] + P1;
                 if (d + 1 <= D - 1 && Lp[d + 1] + P1 < best) best = Lp[d + 1] + P1;
-                if (M + P2 < best) best = M + P2;
+                if (M + p2 < best) best = M + p2;
                 L[d] = (int32_t)C[d] + best - M;
             }
         }
     }
 }
 
-void oracle_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
-                      unsigned path_mask, uint16_t *S)
+void oracle_path_cost(const uint8_t *cost, int H, int W, int D, int P1, int P2, int dir,
+                      int32_t *Lr)
+{
+    path_cost(cost, NULL, 0, H, W, D, P1, P2, dir, Lr);
+}
+
+static void aggregate(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W, int D,
+                      int P1, int P2, unsigned path_mask, uint16_t *S)
 {
     size_t n = (size_t)H * W * D;
     int32_t *Lr = (int32_t *)malloc(n * sizeof(int32_t));
     int32_t *acc = (int32_t *)calloc(n, sizeof(int32_t));
     for (int r = 0; r < 8; ++r) {
         if (!(path_mask & (1u << r))) continue;
-        oracle_path_cost(cost, H, W, D, P1, P2, r, Lr);
+        path_cost(cost, img, pitch, H, W, D, P1, P2, r, Lr);
         for (size_t i = 0; i < n; ++i) acc[i] += Lr[i];
     }
     for (size_t i = 0; i < n; ++i) S[i] = (uint16_t)acc[i];
     free(Lr);
     free(acc);
+}
+
+void oracle_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
+                      unsigned path_mask, uint16_t *S)
+{
+    aggregate(cost, NULL, 0, H, W, D, P1, P2, path_mask, S);
+}
+
+/* Intensity-adaptive large-jump penalty (a variant of the cited SGM method:
+ * the penalty for a disparity jump of more than one step is lowered across
+ * intensity edges of the base image).  Reading: at pixel p with predecessor
+ * p - r on the path, g = |I(p) - I(p - r)| on the base image; the penalty is
+ * P2 if g = 0, else max(P1, floor(P2 / g)).  Path starts have no predecessor
+ * (Lr = C there), so no penalty applies.  img is [H][pitch] uint8. */
+void oracle_path_cost_adaptive(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W,
+                               int D, int P1, int P2, int dir, int32_t *Lr)
+{
+    path_cost(cost, img, pitch, H, W, D, P1, P2, dir, Lr);
+}
+
+void oracle_aggregate_adaptive(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W,
+                               int D, int P1, int P2, unsigned path_mask, uint16_t *S)
+{
+    aggregate(cost, img, pitch, H, W, D, P1, P2, path_mask, S);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -212,6 +255,55 @@ void oracle_no_check(const float *dsubL, int H, int W, uint8_t *valid, float *di
         valid[i] = 1;
         disp[i] = dsubL[i];
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Right-view disparity without a second aggregation (a variant of the cited
+ * SGM method: the match image's disparity at q lies on the diagonal of the
+ * base volume).  Reading: for right pixel (q, y), d*_R is the smallest d in
+ * [0, D) with q + d <= W - 1 that reaches the minimum of S_L(q + d, y, d) over
+ * those d. */
+void oracle_wta_right_diag(const uint16_t *S, int H, int W, int D, int16_t *wtaR)
+{
+    for (int y = 0; y < H; ++y)
+        for (int q = 0; q < W; ++q) {
+            int best = 0;
+            unsigned bestv = S[((size_t)y * W + q) * D + 0];
+            for (int d = 1; d < D && q + d <= W - 1; ++d) {
+                unsigned v = S[((size_t)y * W + (q + d)) * D + d];
+                if (v < bestv) {
+                    bestv = v;
+                    best = d;
+                }
+            }
+            wtaR[(size_t)y * W + q] = (int16_t)best;
+        }
+}
+
+/* 3x3 median filter (the cited method's post-filter of the disparity image).
+ * Reading: out(x, y) = the fifth smallest of the nine values at (x + i, y + j),
+ * i, j in {-1, 0, 1}, with coordinates clamped to the image; it is applied to
+ * the dense sub-pixel map, before the LR mask. */
+void oracle_median3x3(const float *in, int H, int W, float *out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            float v[9];
+            int n = 0;
+            for (int j = -1; j <= 1; ++j)
+                for (int i = -1; i <= 1; ++i)
+                    v[n++] = in[(size_t)clampi(y + j, 0, H - 1) * W + clampi(x + i, 0, W - 1)];
+            for (int a = 1; a < 9; ++a) { /* insertion sort */
+                float t = v[a];
+                int b = a - 1;
+                while (b >= 0 && v[b] > t) {
+                    v[b + 1] = v[b];
+                    --b;
+                }
+                v[b + 1] = t;
+            }
+            out[(size_t)y * W + x] = v[4];
+        }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -330,4 +422,38 @@ void oracle_disparity(const uint8_t *left, const uint8_t *right, int H, int W, i
     oracle_wta(S, H, W, D, wtaL, dsubL);
     oracle_lr_check(wtaL, wtaR, dsubL, H, W, tol, valid, disp);
     free(cl); free(cr); free(cost); free(S); free(wtaR); free(dsubL);
+}
+
+/* The same with the variants: flags bit 0 = right map by the diagonal search
+ * in S_L (no right-view aggregation), bit 1 = 3x3 median of the left sub-pixel
+ * map before the LR mask, bit 2 = intensity-adaptive P2 (each view's base
+ * image: the left image for the left view, the right image for the right). */
+void oracle_disparity_ex(const uint8_t *left, const uint8_t *right, int H, int W, int pitch, int D,
+                         int P1, int P2, unsigned path_mask, int tol, int flags, int16_t *wtaL,
+                         float *disp, uint8_t *valid)
+{
+    size_t npx = (size_t)H * W, n = npx * D;
+    uint64_t *cl = (uint64_t *)malloc(npx * 8), *cr = (uint64_t *)malloc(npx * 8);
+    uint8_t *cost = (uint8_t *)malloc(n);
+    uint16_t *S = (uint16_t *)malloc(n * 2);
+    int16_t *wtaR = (int16_t *)malloc(npx * 2);
+    float *dsubL = (float *)malloc(npx * 4), *med = (float *)malloc(npx * 4);
+    const int adaptive = (flags & 4) != 0;
+    oracle_census(left, H, W, pitch, cl);
+    oracle_census(right, H, W, pitch, cr);
+    if (!(flags & 1)) {
+        oracle_cost(cr, cl, H, W, D, 1, cost);
+        aggregate(cost, adaptive ? right : NULL, pitch, H, W, D, P1, P2, path_mask, S);
+        oracle_wta(S, H, W, D, wtaR, NULL);
+    }
+    oracle_cost(cl, cr, H, W, D, 0, cost);
+    aggregate(cost, adaptive ? left : NULL, pitch, H, W, D, P1, P2, path_mask, S);
+    oracle_wta(S, H, W, D, wtaL, dsubL);
+    if (flags & 1) oracle_wta_right_diag(S, H, W, D, wtaR);
+    if (flags & 2) {
+        oracle_median3x3(dsubL, H, W, med);
+        memcpy(dsubL, med, npx * 4);
+    }
+    oracle_lr_check(wtaL, wtaR, dsubL, H, W, tol, valid, disp);
+    free(cl); free(cr); free(cost); free(S); free(wtaR); free(dsubL); free(med);
 }
