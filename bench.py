@@ -363,6 +363,47 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
             "sceneflow_density_learned": both(out["valid"])}
 
 
+def diag_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
+    """Plain frame whose right maps come from the diagonal search in the left
+    volumes (right-view aggregations skipped): fps, speed-up over the full plain
+    frame, agreement of its masks with the full LR check, and its kernel times."""
+    import torch
+
+    from paper_1801_04720_amd import _lib
+    from paper_1801_04720_amd.pipeline import FusedFrame
+
+    tuning = None
+    if not args.no_autotune:
+        from paper_1801_04720_amd import batch
+
+        tuning, _ = batch.autotune(H, W, D, nviews=2,
+                                   cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+    dp = FusedFrame(H, W, D, diag=True, tuning=tuning, device=dev)
+    for _ in range(args.warmup):
+        dp.run(*inputs)
+    torch.cuda.synchronize()
+    lib = _lib.lib()
+    _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = dp.run(*inputs)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+    lib.sf_prof_disable()
+    kern = {}
+    for name in ["cost", "sgm_tasks", "wta_diag"]:
+        tot, n = kernel_ms(lib, name)
+        if n:
+            kern[name] = tot / n
+    plain = plain_pipe.run(*inputs)
+    torch.cuda.synchronize()
+    agree = [float((out[k] == plain[k]).float().mean().item()) for k in ("valid0", "valid1")]
+    return {"fps_diag": 1e3 / ms, "ms_diag": ms, "speedup_diag_vs_plain": ms_plain / ms,
+            "diag_mask_agreement_t0_t1": agree, "diag_kernels_avg_ms": kern,
+            "sceneflow_density_diag": float((out["valid"] & 1).float().mean().item())}
+
+
 def bench_peaks(args, dev):
     """Measured ceilings: HBM stream rates (2 GiB buffers, far above the 256 MB
     last-level cache), the same copy on a 64 MiB buffer that the last-level cache
@@ -415,6 +456,8 @@ def main():
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
+    ap.add_argument("--no-diag", action="store_true",
+                    help="skip the leg whose right maps come from the diagonal search")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default aggregation tuning instead of the autotuner's choice")
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
@@ -556,6 +599,8 @@ def main():
     }
     if not args.no_learned and args.pipeline != "stages":
         res.update(learned_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
+    if not args.no_diag and args.pipeline != "stages":
+        res.update(diag_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)

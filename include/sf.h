@@ -122,6 +122,32 @@ int sf_wta_lr(const uint16_t *S_left, const uint16_t *S_right, const uint8_t *im
               float *disp, uint8_t *valid, float *feat, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Variants of the cited SGM method (the paper's disparity step names SGM and
+ * its left-right check; these are that method's own options).
+ *
+ * sf_wta_right_diag: the right view's disparity without a right-view
+ * aggregation, found on the diagonal of the left volume:
+ *   d*_R(q, y) = smallest d in [0, D) with q + d <= W-1 minimising S_L(q + d, y, d)
+ *   S_left [H][W][D] uint16;  wta_right [H][W] int16 (output).
+ *   Supported D: [1, SF_DMAX].  Errors: SF_EINVAL.
+ *
+ * sf_lr_check: the left-right check of sf_wta_lr on given maps:
+ *   valid = q = x - wta_left >= 0 and |wta_left(x, y) - wta_right(q, y)| <= lr_tol;
+ *   disp = dsub where valid, -1.0f elsewhere.
+ *   wta_left, wta_right [H][W] int16; dsub [H][W] float; valid [H][W] uint8 and
+ *   disp [H][W] float (outputs).  Errors: SF_EINVAL.
+ *
+ * sf_median3x3: 3x3 median post-filter of a disparity map:
+ *   out(x, y) = 5th smallest of in(x+i, y+j), i, j in {-1, 0, 1}, coordinates
+ *   clamped to the image (bit-exact: the result is one of the nine inputs);
+ *   with mask != NULL, out = -1.0f where mask is 0.  in, out [H][W] float,
+ *   distinct buffers; mask [H][W] uint8 or NULL.  Errors: SF_EINVAL. */
+int sf_wta_right_diag(const uint16_t *S_left, int H, int W, int D, int16_t *wta_right, void *stream);
+int sf_lr_check(const int16_t *wta_left, const int16_t *wta_right, const float *dsub, int H, int W,
+                int lr_tol, uint8_t *valid, float *disp, void *stream);
+int sf_median3x3(const float *in, const uint8_t *mask, int H, int W, float *out, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Combination and triangulation (Sec. 3.3).
  * For each pixel x = (x, y): (u, v) = flow, x' = x + u, y' = y + v.
  * S(x) = (u, v, d0 = disp0(x), d1) is defined iff valid0(x), 0 <= x' <= W-1 and
@@ -180,11 +206,18 @@ int sf_plan_destroy(sf_plan plan);
  *   flags: SF_FRAME_PERSISTENT = persistent aggregation blocks pulling tasks
  *          from a counter (same results); SF_FRAME_LEARNED = the learned
  *          frame (sf_frame_run_learned): the right-view aggregations are
- *          skipped and the LR check is replaced by the network's mask.
+ *          skipped and the LR check is replaced by the network's mask;
+ *          SF_FRAME_DIAG = plain frame whose right maps come from the
+ *          diagonal search in the left volumes (sf_wta_right_diag), so the
+ *          right-view aggregations are skipped (not with LEARNED; W <= 4096);
+ *          SF_FRAME_MEDIAN = each left map's sub-pixel disparities pass the
+ *          3x3 median (sf_median3x3) before the mask is applied.
  * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (device table upload). */
 #define SF_FRAME_PERSISTENT 1
 #define SF_FRAME_LEARNED 2
+#define SF_FRAME_DIAG 4
+#define SF_FRAME_MEDIAN 8
 int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
                          const sf_agg_tuning *tuning /* host, NULL = default */, sf_plan *plan);
 /* L0, R0, L1, R1 [H][pitch] uint8; flow [H][W][2]; cam host pointer or NULL.

@@ -77,6 +77,9 @@ SIGNATURES = {
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),
+    "sf_wta_right_diag": (I, [P, I, I, I, P, P]),
+    "sf_lr_check": (I, [P, P, P, I, I, I, P, P, P]),
+    "sf_median3x3": (I, [P, P, I, I, P, P]),
     "sf_probe_stream": (I, [P, P, SZ, I, P]),
     "sf_probe_pk_u16": (I, [P, I, I, P]),
 }

@@ -161,14 +161,47 @@ class Plan:
             pass
 
 
-FRAME_PERSISTENT, FRAME_LEARNED = 1, 2
+def wta_right_diag(S_left, out=None, stream=None):
+    """Right-view d* by the diagonal search in the left volume (no right aggregation)."""
+    H, W, D = S_left.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.int16, device=S_left.device)
+    check(lib().sf_wta_right_diag(_ptr(S_left), H, W, D, _ptr(out), _stream(stream)))
+    return out
+
+
+def lr_check(wta_left, wta_right, dsub, lr_tol: int = 1, out=None, stream=None):
+    """LR check of given maps -> {"valid", "disp"}."""
+    H, W = wta_left.shape
+    if out is None:
+        out = {"valid": torch.empty((H, W), dtype=torch.uint8, device=wta_left.device),
+               "disp": torch.empty((H, W), dtype=torch.float32, device=wta_left.device)}
+    check(lib().sf_lr_check(_ptr(wta_left), _ptr(wta_right), _ptr(dsub), H, W, lr_tol,
+                            _ptr(out["valid"]), _ptr(out["disp"]), _stream(stream)))
+    return out
+
+
+def median3x3(m, mask=None, out=None, stream=None):
+    """3x3 median (clamp-to-edge) of a float [H][W] map; -1 where mask == 0."""
+    H, W = m.shape
+    if out is None:
+        out = torch.empty_like(m)
+    check(lib().sf_median3x3(_ptr(m), _ptr(mask), H, W, _ptr(out), _stream(stream)))
+    return out
+
+
+FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN = 1, 2, 4, 8
 
 
 def frame_plan(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
-               persistent: bool = False, learned: bool = False, tuning=None) -> Plan:
-    """tuning: an _lib.SfAggTuning for the aggregation launch (None = default)."""
+               persistent: bool = False, learned: bool = False, tuning=None, diag: bool = False,
+               median: bool = False) -> Plan:
+    """tuning: an _lib.SfAggTuning for the aggregation launch (None = default).
+    diag: right maps by the diagonal search (plain frames); median: 3x3 median of
+    the left sub-pixel maps before the mask."""
     h = ct.c_void_p()
-    flags = (FRAME_PERSISTENT if persistent else 0) | (FRAME_LEARNED if learned else 0)
+    flags = ((FRAME_PERSISTENT if persistent else 0) | (FRAME_LEARNED if learned else 0) |
+             (FRAME_DIAG if diag else 0) | (FRAME_MEDIAN if median else 0))
     tp = ct.byref(tuning) if tuning is not None else None
     check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, tp, ct.byref(h)))
     return Plan(h)

@@ -63,8 +63,12 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_frame_plan_create: lr_tol < 0");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED,
                "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
-    SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED)) == 0, SF_EINVAL,
-               "sf_frame_plan_create: unknown flags");
+    SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED | SF_FRAME_DIAG | SF_FRAME_MEDIAN)) == 0,
+               SF_EINVAL, "sf_frame_plan_create: unknown flags");
+    SF_REQUIRE(!((flags & SF_FRAME_DIAG) && (flags & SF_FRAME_LEARNED)), SF_EINVAL,
+               "sf_frame_plan_create: SF_FRAME_DIAG and SF_FRAME_LEARNED exclude each other");
+    SF_REQUIRE(!(flags & SF_FRAME_DIAG) || W <= 4096, SF_EUNSUPPORTED,
+               "sf_frame_plan_create: SF_FRAME_DIAG needs W <= 4096");
     sf_agg_tuning tun{16, 8, 0, (flags & SF_FRAME_PERSISTENT) ? 8 : 0};
     if (tuning) {
         tun = *tuning;
@@ -80,14 +84,16 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     if (!p) return fail(SF_ENOMEM, "sf_frame_plan_create: out of host memory");
     p->kind = Plan::FRAME;
     p->learned = (flags & SF_FRAME_LEARNED) != 0;
+    p->diag = (flags & SF_FRAME_DIAG) != 0;
+    p->median = (flags & SF_FRAME_MEDIAN) != 0;
     p->H = H;
     p->W = W;
     p->D = D;
     p->P1 = P1;
     p->P2 = P2;
     p->tol = lr_tol;
-    // Views aggregated: plain = L0, R0, L1, R1 bases; learned = L0, L1 bases only.
-    const int nv = p->learned ? 2 : 4;
+    // Views aggregated: plain = L0, R0, L1, R1 bases; learned and diag = L0, L1 bases only.
+    const int nv = (p->learned || p->diag) ? 2 : 4;
     const size_t npx = (size_t)H * W, ncell = npx * D;
     size_t off = 0;
     for (int i = 0; i < 4; ++i) { p->off_cen[i] = off; off += align256(npx * 8); }
@@ -95,9 +101,10 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     for (int i = 0; i < nv; ++i) { p->off_slab[i] = off; off += align256(8 * ncell); }
     for (int i = 0; i < 2; ++i) { p->off_wtar[i] = off; off += align256(npx * 2); }
     for (int i = 0; i < 2; ++i) { p->off_wtal[i] = off; off += align256(npx * 2); }
+    if (p->learned || p->median)
+        for (int i = 0; i < 2; ++i) { p->off_dsub[i] = off; off += align256(npx * 4); }
     if (p->learned) {
         p->off_feat = off; off += align256(2 * npx * 16);
-        for (int i = 0; i < 2; ++i) { p->off_dsub[i] = off; off += align256(npx * 4); }
         for (int i = 0; i < 2; ++i) { p->off_vtmp[i] = off; off += align256(npx); }
         p->off_logit = off; off += align256(2 * npx * 4);
         p->off_lrws = off; off += align256(lrnet_forward_ws_bytes(2, H, W));
@@ -178,53 +185,90 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     int rc = launch_census(ca, st);
     if (rc) return rc;
 
-    // Views: 0 = L0 base, 1 = R0 base, 2 = L1 base, 3 = R1 base.
-    CostArgs co{};
-    for (int t = 0; t < 2; ++t) {
-        co.base[2 * t] = cen[2 * t];      co.match[2 * t] = cen[2 * t + 1];  co.right[2 * t] = 0;
-        co.base[2 * t + 1] = cen[2 * t + 1]; co.match[2 * t + 1] = cen[2 * t]; co.right[2 * t + 1] = 1;
-    }
-    for (int i = 0; i < 4; ++i) co.cost[i] = at(p->off_cost[i]);
-    co.n = 4; co.H = H; co.W = W; co.D = D;
-    rc = launch_cost(co, st);
-    if (rc) return rc;
-
-    rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
-                          p->persistent_blocks, st,
-                          p->tuning.chains_per_block, p->tuning.prefetch);
-    if (rc) return rc;
-
+    float *dsp[2] = {disp0, disp1};
+    uint8_t *vld[2] = {valid0, valid1};
     int16_t *wtar[2], *wtal[2];
     for (int t = 0; t < 2; ++t) {
         wtar[t] = reinterpret_cast<int16_t *>(at(p->off_wtar[t]));
         wtal[t] = reinterpret_cast<int16_t *>(at(p->off_wtal[t]));
     }
-    WtaArgs wr{};
-    for (int t = 0; t < 2; ++t) {
-        WtaView &v = wr.v[t];
-        v.slab = at(p->off_slab[2 * t + 1]);
-        v.wta = wtar[t];
-        v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 1;
-    }
-    wr.n = 2;
-    rc = launch_wta_slabs(wr, st);
-    if (rc) return rc;
+    // With the median, the WTA writes the dense sub-pixel map to scratch and the
+    // median kernel writes the masked result.
+    float *wdsp[2];
+    for (int t = 0; t < 2; ++t)
+        wdsp[t] = p->median ? reinterpret_cast<float *>(at(p->off_dsub[t])) : dsp[t];
 
-    WtaArgs wl{};
-    float *dsp[2] = {disp0, disp1};
-    uint8_t *vld[2] = {valid0, valid1};
-    for (int t = 0; t < 2; ++t) {
-        WtaView &v = wl.v[t];
-        v.slab = at(p->off_slab[2 * t]);
-        v.wta_r = wtar[t];
-        v.wta = wtal[t];
-        v.disp = dsp[t];
-        v.valid = vld[t];
-        v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 0;
+    if (p->diag) {
+        // Views: 0 = L0 base, 1 = L1 base; right maps by the diagonal search.
+        CostArgs co{};
+        for (int t = 0; t < 2; ++t) {
+            co.base[t] = cen[2 * t];
+            co.match[t] = cen[2 * t + 1];
+            co.right[t] = 0;
+            co.cost[t] = at(p->off_cost[t]);
+        }
+        co.n = 2; co.H = H; co.W = W; co.D = D;
+        if ((rc = launch_cost(co, st))) return rc;
+        if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
+                                   p->persistent_blocks, st, p->tuning.chains_per_block,
+                                   p->tuning.prefetch)))
+            return rc;
+        WtaArgs wd{};
+        for (int t = 0; t < 2; ++t) {
+            WtaView &v = wd.v[t];
+            v.slab = at(p->off_slab[t]);
+            v.wta = wtal[t];
+            v.wta_r_out = wtar[t];
+            v.disp = wdsp[t];
+            v.valid = vld[t];
+            v.dense = p->median ? 1 : 0;
+            v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol;
+        }
+        wd.n = 2;
+        if ((rc = launch_wta_diag_slabs(wd, st))) return rc;
+    } else {
+        // Views: 0 = L0 base, 1 = R0 base, 2 = L1 base, 3 = R1 base.
+        CostArgs co{};
+        for (int t = 0; t < 2; ++t) {
+            co.base[2 * t] = cen[2 * t];      co.match[2 * t] = cen[2 * t + 1];  co.right[2 * t] = 0;
+            co.base[2 * t + 1] = cen[2 * t + 1]; co.match[2 * t + 1] = cen[2 * t]; co.right[2 * t + 1] = 1;
+        }
+        for (int i = 0; i < 4; ++i) co.cost[i] = at(p->off_cost[i]);
+        co.n = 4; co.H = H; co.W = W; co.D = D;
+        if ((rc = launch_cost(co, st))) return rc;
+
+        if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
+                                   p->persistent_blocks, st, p->tuning.chains_per_block,
+                                   p->tuning.prefetch)))
+            return rc;
+
+        WtaArgs wr{};
+        for (int t = 0; t < 2; ++t) {
+            WtaView &v = wr.v[t];
+            v.slab = at(p->off_slab[2 * t + 1]);
+            v.wta = wtar[t];
+            v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 1;
+        }
+        wr.n = 2;
+        if ((rc = launch_wta_slabs(wr, st))) return rc;
+
+        WtaArgs wl{};
+        for (int t = 0; t < 2; ++t) {
+            WtaView &v = wl.v[t];
+            v.slab = at(p->off_slab[2 * t]);
+            v.wta_r = wtar[t];
+            v.wta = wtal[t];
+            v.disp = wdsp[t];
+            v.valid = vld[t];
+            v.dense = p->median ? 1 : 0;
+            v.nslab = 8; v.H = H; v.W = W; v.D = D; v.P2 = p->P2; v.tol = p->tol; v.right_only = 0;
+        }
+        wl.n = 2;
+        if ((rc = launch_wta_slabs(wl, st))) return rc;
     }
-    wl.n = 2;
-    rc = launch_wta_slabs(wl, st);
-    if (rc) return rc;
+    if (p->median)
+        for (int t = 0; t < 2; ++t)
+            if ((rc = launch_median_mask(wdsp[t], vld[t], H, W, dsp[t], st))) return rc;
 
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
 }
@@ -297,11 +341,13 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st))) return rc;
     float *dsp[2] = {disp0, disp1};
     uint8_t *vld[2] = {valid0, valid1};
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < 2; ++t) {
+        const float *dsub = reinterpret_cast<const float *>(at(p->off_dsub[t]));
         if ((rc = launch_lr_mask(logits + (size_t)t * H * W,
-                                 reinterpret_cast<const int16_t *>(at(p->off_wtal[t])),
-                                 reinterpret_cast<const float *>(at(p->off_dsub[t])), H, W, vld[t],
-                                 dsp[t], st)))
+                                 reinterpret_cast<const int16_t *>(at(p->off_wtal[t])), dsub, H, W,
+                                 vld[t], dsp[t], st)))
             return rc;
+        if (p->median && (rc = launch_median_mask(dsub, vld[t], H, W, dsp[t], st))) return rc;
+    }
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
 }

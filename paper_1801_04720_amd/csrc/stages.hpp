@@ -31,6 +31,9 @@ struct CostArgs {
 // WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8).
 // right_only: write d* to wta only.  Otherwise d*, sub-pixel disparity, the LR
 // check against wta_r (NULL: no check, valid := 1) and optional features.
+// dense: disp holds the sub-pixel disparity everywhere (valid still written).
+// The diagonal-search launch ignores wta_r and may write the right map to
+// wta_r_out.
 struct WtaView {
     const uint8_t *slab;
     const int16_t *wta_r;
@@ -39,7 +42,8 @@ struct WtaView {
     float *disp;
     uint8_t *valid;
     float *feat;
-    int nslab, H, W, D, P2, tol, pitch, right_only;
+    int16_t *wta_r_out;
+    int nslab, H, W, D, P2, tol, pitch, right_only, dense;
 };
 
 struct WtaArgs {
@@ -50,7 +54,11 @@ struct WtaArgs {
 
 int launch_census(const CensusArgs &a, hipStream_t st);
 int launch_cost(const CostArgs &a, hipStream_t st);
-int launch_wta_slabs(WtaArgs &a, hipStream_t st);  // fills blk0
+int launch_wta_slabs(WtaArgs &a, hipStream_t st);       // fills blk0
+int launch_wta_diag_slabs(WtaArgs &a, hipStream_t st);  // fills blk0; W <= 4096
+// out = 3x3 median of dense (clamp-to-edge), or -1 where mask is 0 (mask may be NULL).
+int launch_median_mask(const float *dense, const uint8_t *mask, int H, int W, float *out,
+                       hipStream_t st);
 size_t lrnet_forward_ws_bytes(int B, int H, int W);
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
                   uint8_t *ws, hipStream_t st);

@@ -115,31 +115,22 @@ __device__ __forceinline__ int slab_pos_to_d(int pos)
     return q * K + (e >> 1) + (e & 1) * (K >> 1);
 }
 
+// Packed u16 sums of the first ns slabs at pixel px for lane j of a 16-lane
+// group (byte positions [8c, 8c + 8), c = j and j + 16), and the disparity of
+// each position.  All slab loads of the lane are issued before any is used
+// (slabs past ns re-read the last one and are masked to zero), so a wave keeps
+// up to 16 loads in flight.
 template <int K>
-__global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
+__device__ __forceinline__ void slab_sums(const uint8_t *__restrict__ slab, size_t cells, int px,
+                                          int j, int ns, uint32_t (&sv)[2][4], int (&dd)[2][8])
 {
-    int vi = 0;
-    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
-    const WtaView v = a.v[vi];
-    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const int px = ((int)blockIdx.x - a.blk0[vi]) * WTA_PPB + q;
-    const int npx = v.H * v.W;
-    if (px >= npx) return;
     constexpr int D = 16 * K;
-    const size_t cells = (size_t)npx * D;
-    uint32_t sv[2][4];
-    int dd[2][8];
-    uint32_t best = 0xFFFFFFFFu;
-    // All slab loads of the lane are issued before any is used (slabs past
-    // nslab re-read the last one and are masked to zero), so each wave keeps
-    // up to 16 loads in flight.
-    const int ns = v.nslab;
     u32x2 w[2][8];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
         if (8 * c < D) {
-            const uint8_t *src = v.slab + (size_t)px * D + 8 * c;
+            const uint8_t *src = slab + (size_t)px * D + 8 * c;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 w[i][k] = __builtin_nontemporal_load(
@@ -163,21 +154,25 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
                 sv[i][2] += __builtin_amdgcn_perm(0u, hi, 0x0c010c00u);
                 sv[i][3] += __builtin_amdgcn_perm(0u, hi, 0x0c030c02u);
             }
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
-                best = min(best, (val << 9) | (uint32_t)dd[i][e]);
-            }
         }
     }
-    const uint32_t key = row16_min(best);
-    const int ds = (int)(key & 511u);
-    const uint32_t smin = key >> 9;
-    if (v.right_only) {
-        if (j == 0) v.wta[px] = (int16_t)ds;
-        return;
-    }
-    uint32_t av = 0, cv = 0, s2 = 0xFFFFFFFFu;
+}
+
+__device__ __forceinline__ uint32_t sv_val(const uint32_t (&sv)[2][4], int i, int e)
+{
+    return (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
+}
+
+// S(d* - 1), S(d* + 1) and (optionally) the minimum over |d - d*| >= 2, each
+// left in every lane of the group.
+template <int K, bool S2>
+__device__ __forceinline__ void neighbours(const uint32_t (&sv)[2][4], const int (&dd)[2][8], int j,
+                                           int ds, uint32_t &av, uint32_t &cv, uint32_t &s2)
+{
+    constexpr int D = 16 * K;
+    av = 0;
+    cv = 0;
+    s2 = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
@@ -185,24 +180,68 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int d = dd[i][e];
-                const uint32_t val = (e & 1) ? (sv[i][e >> 1] >> 16) : (sv[i][e >> 1] & 0xFFFFu);
+                const uint32_t val = sv_val(sv, i, e);
                 if (d == ds - 1) av = val;
                 if (d == ds + 1) cv = val;
-                const int gap = d > ds ? d - ds : ds - d;
-                if (gap >= 2) s2 = min(s2, val);
+                if (S2) {
+                    const int gap = d > ds ? d - ds : ds - d;
+                    if (gap >= 2) s2 = min(s2, val);
+                }
             }
         }
     }
     av = row16_max(av);
     cv = row16_max(cv);
-    s2 = row16_min(s2);
-    if (j != 0) return;
-    const int y = px / v.W, x = px - y * v.W;
+    if (S2) s2 = row16_min(s2);
+}
+
+// Parabolic sub-pixel disparity from S(d*-1), S(d*), S(d*+1).
+__device__ __forceinline__ float subpixel(int ds, int D, uint32_t av, uint32_t smin, uint32_t cv)
+{
     float sub = (float)ds;
     if (ds > 0 && ds < D - 1) {
         const int den = (int)av - 2 * (int)smin + (int)cv;
         if (den > 0) sub = (float)ds + (float)((int)av - (int)cv) / (float)(2 * den);
     }
+    return sub;
+}
+
+template <int K>
+__global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
+{
+    int vi = 0;
+    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
+    const WtaView v = a.v[vi];
+    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const int px = ((int)blockIdx.x - a.blk0[vi]) * WTA_PPB + q;
+    const int npx = v.H * v.W;
+    if (px >= npx) return;
+    constexpr int D = 16 * K;
+    uint32_t sv[2][4];
+    int dd[2][8];
+    slab_sums<K>(v.slab, (size_t)npx * D, px, j, v.nslab, sv, dd);
+    uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+        if (8 * (j + 16 * i) < D) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) best = min(best, (sv_val(sv, i, e) << 9) | (uint32_t)dd[i][e]);
+        }
+    const uint32_t key = row16_min(best);
+    const int ds = (int)(key & 511u);
+    const uint32_t smin = key >> 9;
+    if (v.right_only) {
+        if (j == 0) v.wta[px] = (int16_t)ds;
+        return;
+    }
+    uint32_t av, cv, s2;
+    if (v.feat)
+        neighbours<K, true>(sv, dd, j, ds, av, cv, s2);
+    else
+        neighbours<K, false>(sv, dd, j, ds, av, cv, s2);
+    if (j != 0) return;
+    const int y = px / v.W, x = px - y * v.W;
+    const float sub = subpixel(ds, D, av, smin, cv);
     int ok = 1;
     if (v.wta_r) {
         const int qx = x - ds;
@@ -214,7 +253,7 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         }
     }
     if (v.wta) v.wta[px] = (int16_t)ds;
-    v.disp[px] = ok ? sub : -1.0f;
+    v.disp[px] = (ok || v.dense) ? sub : -1.0f;
     v.valid[px] = (uint8_t)ok;
     if (v.feat) {
         if (s2 == 0xFFFFFFFFu) s2 = smin;
@@ -224,6 +263,76 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         f.z = (float)smin / (float)(8 * (SF_CMAX + v.P2));
         f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
         reinterpret_cast<float4 *>(v.feat)[px] = f;
+    }
+}
+
+// Left WTA and the right map by diagonal search in one pass over the left
+// slabs (a variant of the cited SGM method: the right view's disparity at q is
+// the d minimising S_L(q + d, d), smallest d on ties, over q + d <= W - 1).
+// One block per image row: each 16-lane group sums the slabs of one pixel x,
+// takes its left WTA, and offers the key S_L(x, d) * 512 + d to the right
+// pixel q = x - d with an LDS atomic minimum.  Once the whole row has been
+// offered, the LR check reads the finished right map from LDS.
+constexpr int DIAG_NT = 512;
+constexpr int DIAG_MAXW = 4096;
+
+template <int K>
+__global__ __launch_bounds__(DIAG_NT) void wta_diag_slab_kernel(WtaArgs a)
+{
+    extern __shared__ uint32_t dg_lds[];
+    int vi = 0;
+    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
+    const WtaView v = a.v[vi];
+    const int y = (int)blockIdx.x - a.blk0[vi];
+    const int W = v.W;
+    constexpr int D = 16 * K;
+    uint32_t *bestr = dg_lds;                                  // [W] right-map keys
+    float *dsl = reinterpret_cast<float *>(dg_lds + W);        // [W] left sub-pixel disparity
+    int16_t *dl = reinterpret_cast<int16_t *>(dg_lds + 2 * W);  // [W] left d*
+    for (int i = threadIdx.x; i < W; i += DIAG_NT) bestr[i] = 0xFFFFFFFFu;
+    __syncthreads();
+    const int g = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const size_t cells = (size_t)v.H * W * D;
+    for (int x = g; x < W; x += DIAG_NT / 16) {
+        uint32_t sv[2][4];
+        int dd[2][8];
+        slab_sums<K>(v.slab, cells, y * W + x, j, v.nslab, sv, dd);
+        uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            if (8 * (j + 16 * i) < D) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t k = (sv_val(sv, i, e) << 9) | (uint32_t)dd[i][e];
+                    best = min(best, k);
+                    const int q = x - dd[i][e];
+                    if (q >= 0) atomicMin(&bestr[q], k);
+                }
+            }
+        const uint32_t key = row16_min(best);
+        const int ds = (int)(key & 511u);
+        uint32_t av, cv, s2;
+        neighbours<K, false>(sv, dd, j, ds, av, cv, s2);
+        if (j == 0) {
+            dl[x] = (int16_t)ds;
+            dsl[x] = subpixel(ds, D, av, key >> 9, cv);
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < W; x += DIAG_NT) {
+        const int ds = dl[x];
+        const int qx = x - ds;
+        int ok = 0;
+        if (qx >= 0) {
+            int diff = ds - (int)(bestr[qx] & 511u);
+            diff = diff < 0 ? -diff : diff;
+            ok = diff <= v.tol;
+        }
+        const size_t px = (size_t)y * W + x;
+        if (v.wta) v.wta[px] = (int16_t)ds;
+        if (v.wta_r_out) v.wta_r_out[px] = (int16_t)(bestr[x] & 511u);
+        v.disp[px] = (ok || v.dense) ? dsl[x] : -1.0f;
+        v.valid[px] = (uint8_t)ok;
     }
 }
 
@@ -253,6 +362,130 @@ int launch_wta_slabs(WtaArgs &a, hipStream_t st)
     default: return fail(SF_EUNSUPPORTED, "launch_wta_slabs: unsupported D");
     }
     return launch_status("wta_slab_kernel");
+}
+
+int launch_wta_diag_slabs(WtaArgs &a, hipStream_t st)
+{
+    long long tot = 0;
+    for (int i = 0; i < a.n; ++i) {
+        a.blk0[i] = (int)tot;
+        tot += a.v[i].H;
+    }
+    for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
+    if (tot <= 0) return SF_OK;
+    int maxw = 0;
+    for (int i = 0; i < a.n; ++i) {
+        if (a.v[i].D != a.v[0].D) return fail(SF_EINVAL, "launch_wta_diag_slabs: views of one launch need one D");
+        if (a.v[i].nslab < 1 || a.v[i].nslab > 8) return fail(SF_EINVAL, "launch_wta_diag_slabs: nslab must be in [1, 8]");
+        if (a.v[i].W > DIAG_MAXW) return fail(SF_EUNSUPPORTED, "launch_wta_diag_slabs: W > 4096");
+        maxw = max(maxw, a.v[i].W);
+    }
+    const size_t lds = (size_t)maxw * (4 + 4 + 2);
+    ProfScope prof("wta_diag", st);
+    switch (a.v[0].D / 16) {
+#define SF_DIAG_CASE(KK)                                                                            \
+    case KK:                                                                                        \
+        hipLaunchKernelGGL(wta_diag_slab_kernel<KK>, dim3((unsigned)tot), dim3(DIAG_NT), lds, st, a); \
+        break;
+        SF_DIAG_CASE(2) SF_DIAG_CASE(4) SF_DIAG_CASE(6) SF_DIAG_CASE(8) SF_DIAG_CASE(10)
+        SF_DIAG_CASE(12) SF_DIAG_CASE(14) SF_DIAG_CASE(16)
+#undef SF_DIAG_CASE
+    default: return fail(SF_EUNSUPPORTED, "launch_wta_diag_slabs: unsupported D");
+    }
+    return launch_status("wta_diag_slab_kernel");
+}
+
+// d*_R by the diagonal search on a u16 volume S_L (the stage entry point).
+// One 16-lane group per right pixel q; lane j scans d = j, j + 16, ...
+__global__ __launch_bounds__(WTA_NT) void wta_diag_right_kernel(const uint16_t *__restrict__ S,
+                                                               int H, int W, int D,
+                                                               int16_t *__restrict__ wta_r)
+{
+    const int px = blockIdx.x * WTA_PPB + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (px >= H * W) return;
+    const int y = px / W, q = px - y * W;
+    uint32_t best = 0xFFFFFFFFu;
+    for (int d = j; d < D && q + d < W; d += 16)
+        best = min(best, ((uint32_t)S[((size_t)y * W + q + d) * D + d] << 9) | (uint32_t)d);
+    best = row16_min(best);
+    if (j == 0) wta_r[px] = (int16_t)(best & 511u);
+}
+
+// LR mask: valid iff x - d*_L >= 0 and |d*_L - d*_R(x - d*_L)| <= tol;
+// disp = dsub where valid, else -1.
+__global__ __launch_bounds__(256) void lr_check_kernel(const int16_t *__restrict__ wl,
+                                                       const int16_t *__restrict__ wr,
+                                                       const float *__restrict__ dsub, int H, int W,
+                                                       int tol, uint8_t *__restrict__ valid,
+                                                       float *__restrict__ disp)
+{
+    const int px = blockIdx.x * 256 + threadIdx.x;
+    if (px >= H * W) return;
+    const int y = px / W, x = px - y * W;
+    const int dl = wl[px], q = x - dl;
+    int ok = 0;
+    if (q >= 0) {
+        int diff = dl - (int)wr[(size_t)y * W + q];
+        diff = diff < 0 ? -diff : diff;
+        ok = diff <= tol;
+    }
+    valid[px] = (uint8_t)ok;
+    disp[px] = ok ? dsub[px] : -1.0f;
+}
+
+// 3x3 median with clamp-to-edge; with a mask, pixels outside it get -1.  The
+// 16x16 tile plus a one-pixel halo is staged in LDS; the median of nine is a
+// fixed network of 19 compare-exchanges (min/max return one of their inputs,
+// so the result is one of the nine values bit for bit).
+constexpr int MED_T = 16;
+
+__device__ __forceinline__ void cx(float &a, float &b)
+{
+    const float lo = fminf(a, b), hi = fmaxf(a, b);
+    a = lo;
+    b = hi;
+}
+
+__global__ __launch_bounds__(MED_T *MED_T) void median3x3_kernel(const float *__restrict__ in,
+                                                                 const uint8_t *__restrict__ mask,
+                                                                 int H, int W,
+                                                                 float *__restrict__ out)
+{
+    __shared__ float t[MED_T + 2][MED_T + 2];
+    const int x0 = blockIdx.x * MED_T, y0 = blockIdx.y * MED_T;
+    const int tid = threadIdx.y * MED_T + threadIdx.x;
+    for (int i = tid; i < (MED_T + 2) * (MED_T + 2); i += MED_T * MED_T) {
+        const int ly = i / (MED_T + 2), lx = i - ly * (MED_T + 2);
+        const int gy = min(max(y0 + ly - 1, 0), H - 1), gx = min(max(x0 + lx - 1, 0), W - 1);
+        t[ly][lx] = in[(size_t)gy * W + gx];
+    }
+    __syncthreads();
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    if (x >= W || y >= H) return;
+    float p[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p[3 * j + i] = t[threadIdx.y + j][threadIdx.x + i];
+    cx(p[1], p[2]); cx(p[4], p[5]); cx(p[7], p[8]);
+    cx(p[0], p[1]); cx(p[3], p[4]); cx(p[6], p[7]);
+    cx(p[1], p[2]); cx(p[4], p[5]); cx(p[7], p[8]);
+    cx(p[0], p[3]); cx(p[5], p[8]); cx(p[4], p[7]);
+    cx(p[3], p[6]); cx(p[1], p[4]); cx(p[2], p[5]);
+    cx(p[4], p[7]); cx(p[4], p[2]); cx(p[6], p[4]);
+    cx(p[4], p[2]);
+    const size_t px = (size_t)y * W + x;
+    out[px] = (!mask || mask[px]) ? p[4] : -1.0f;
+}
+
+int launch_median_mask(const float *dense, const uint8_t *mask, int H, int W, float *out,
+                       hipStream_t st)
+{
+    dim3 grid((W + MED_T - 1) / MED_T, (H + MED_T - 1) / MED_T);
+    ProfScope prof("median3x3", st);
+    hipLaunchKernelGGL(median3x3_kernel, grid, dim3(MED_T, MED_T), 0, st, dense, mask, H, W, out);
+    return launch_status("median3x3_kernel");
 }
 
 }  // namespace sf
@@ -288,4 +521,44 @@ extern "C" int sf_wta_lr(const uint16_t *S_left, const uint16_t *S_right, const 
                        S_right ? wta_right : nullptr, img_left, pitch, H, W, D, P2, lr_tol,
                        wta_left, disp, valid, feat);
     return launch_status("wta_left_kernel");
+}
+
+extern "C" int sf_wta_right_diag(const uint16_t *S_left, int H, int W, int D, int16_t *wta_right,
+                                 void *stream)
+{
+    clear_error();
+    SF_REQUIRE(S_left && wta_right, SF_EINVAL, "sf_wta_right_diag: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_wta_right_diag: H and W must be positive");
+    SF_REQUIRE((long long)H * W <= (1LL << 30), SF_EINVAL, "sf_wta_right_diag: image too large");
+    SF_REQUIRE(D >= 1 && D <= SF_DMAX, SF_EINVAL, "sf_wta_right_diag: D must be in [1, 256]");
+    const int npx = H * W;
+    ProfScope prof("wta_right_diag", as_stream(stream));
+    hipLaunchKernelGGL(wta_diag_right_kernel, dim3((npx + WTA_PPB - 1) / WTA_PPB), dim3(WTA_NT), 0,
+                       as_stream(stream), S_left, H, W, D, wta_right);
+    return launch_status("wta_diag_right_kernel");
+}
+
+extern "C" int sf_lr_check(const int16_t *wta_left, const int16_t *wta_right, const float *dsub,
+                           int H, int W, int lr_tol, uint8_t *valid, float *disp, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(wta_left && wta_right && dsub && valid && disp, SF_EINVAL, "sf_lr_check: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_lr_check: H and W must be positive");
+    SF_REQUIRE((long long)H * W <= (1LL << 30), SF_EINVAL, "sf_lr_check: image too large");
+    SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_lr_check: lr_tol < 0");
+    const int npx = H * W;
+    hipLaunchKernelGGL(lr_check_kernel, dim3((npx + 255) / 256), dim3(256), 0, as_stream(stream),
+                       wta_left, wta_right, dsub, H, W, lr_tol, valid, disp);
+    return launch_status("lr_check_kernel");
+}
+
+extern "C" int sf_median3x3(const float *in, const uint8_t *mask, int H, int W, float *out,
+                            void *stream)
+{
+    clear_error();
+    SF_REQUIRE(in && out, SF_EINVAL, "sf_median3x3: NULL pointer");
+    SF_REQUIRE(in != out, SF_EINVAL, "sf_median3x3: in and out must not be the same buffer");
+    SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_median3x3: H and W must be positive");
+    SF_REQUIRE(H <= 65535 * 16, SF_EINVAL, "sf_median3x3: H too large");
+    return launch_median_mask(in, mask, H, W, out, as_stream(stream));
 }

@@ -14,9 +14,15 @@ from . import api
 
 
 class PlainFrame:
+    """Per-stage frame: every stage is its own C-ABI call.  diag: right maps by
+    the diagonal search in S_L; median: 3x3 median of the left sub-pixel maps
+    before the LR mask."""
+
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
-                 cam=(721.5, 0.54, None, None), path_mask: int = 0xFF, device="cuda:0"):
+                 cam=(721.5, 0.54, None, None), path_mask: int = 0xFF, device="cuda:0",
+                 diag: bool = False, median: bool = False):
         self.H, self.W, self.D = H, W, D
+        self.diag, self.median = diag, median
         self.P1, self.P2, self.tol, self.mask = P1, P2, lr_tol, path_mask
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
@@ -34,15 +40,35 @@ class PlainFrame:
                               "feat": None})
         self.out = {"sf4": e(H, W, 4, dt=torch.float32), "valid": e(H, W, dt=torch.uint8),
                     "xyz0": e(H, W, 3, dt=torch.float32), "motion": e(H, W, 3, dt=torch.float32)}
+        self.dense = e(H, W, dt=torch.float32)
+        self.ones = e(H, W, dt=torch.uint8)
 
     def disparity(self, t: int, left, right, cen_l, cen_r):
         api.census(left, out=cen_l)
         api.census(right, out=cen_r)
-        api.cost(cen_r, cen_l, self.D, True, out=self.cost)
-        api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_right, workspace=self.ws)
+        m = self.maps[t]
+        if not self.diag:
+            api.cost(cen_r, cen_l, self.D, True, out=self.cost)
+            api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_right,
+                              workspace=self.ws)
         api.cost(cen_l, cen_r, self.D, False, out=self.cost)
         api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_left, workspace=self.ws)
-        return api.wta_lr(self.S_left, self.S_right, None, self.P2, self.tol, out=self.maps[t])
+        if not self.diag and not self.median:
+            return api.wta_lr(self.S_left, self.S_right, None, self.P2, self.tol, out=m)
+        # Left WTA without a check (dense sub-pixel map), the right map, then the mask.
+        api.wta_lr(self.S_left, None, None, self.P2, self.tol,
+                   out={"wta_left": m["wta_left"], "disp": self.dense, "valid": self.ones,
+                        "feat": None})
+        if self.diag:
+            api.wta_right_diag(self.S_left, out=m["wta_right"])
+        else:
+            api.wta_lr(self.S_right, None, None, self.P2, self.tol,
+                       out={"wta_left": m["wta_right"], "disp": m["disp"], "valid": m["valid"],
+                            "feat": None})
+        api.lr_check(m["wta_left"], m["wta_right"], self.dense, self.tol, out=m)
+        if self.median:
+            api.median3x3(self.dense, m["valid"], out=m["disp"])
+        return m
 
     def run(self, L0, R0, L1, R1, flow):
         m0 = self.disparity(0, L0, R0, self.cen[0], self.cen[1])
@@ -58,13 +84,14 @@ class FusedFrame:
 
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
                  cam=(721.5, 0.54, None, None), persistent: bool = False, learned_params=None,
-                 tuning=None, device="cuda:0"):
+                 tuning=None, device="cuda:0", diag: bool = False, median: bool = False):
         self.H, self.W, self.D = H, W, D
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
         self.params = learned_params
         self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent,
-                                   learned=learned_params is not None, tuning=tuning)
+                                   learned=learned_params is not None, tuning=tuning, diag=diag,
+                                   median=median)
         dev = torch.device(device)
         e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
         self.ws = e(self.plan.workspace_bytes(), dt=torch.uint8)

@@ -109,3 +109,17 @@ def test_last_error_cleared_by_next_call(L):
     assert L.sf_last_error() != b""
     L.sf_sgm_aggregate(FAKE, 4, 4, 32, 20, 10, 255, FAKE, FAKE, 0, None)
     assert b"P1" in L.sf_last_error()
+
+
+def test_variant_validation(L):
+    expect(L.sf_wta_right_diag(None, 4, 4, 8, FAKE, None), 1, "NULL")
+    expect(L.sf_wta_right_diag(FAKE, 4, 4, 0, FAKE, None), 1, "D must")
+    expect(L.sf_lr_check(FAKE, FAKE, FAKE, 4, 4, -1, FAKE, FAKE, None), 1, "lr_tol")
+    expect(L.sf_lr_check(FAKE, None, FAKE, 4, 4, 1, FAKE, FAKE, None), 1, "NULL")
+    expect(L.sf_median3x3(FAKE, None, 4, 4, FAKE, None), 1, "must not be the same")
+    expect(L.sf_median3x3(FAKE, None, 0, 4, ct.c_void_p(0x2000), None), 1, "positive")
+    plan = ct.c_void_p()
+    # Diagonal search and learned mask exclude each other; the diagonal kernel keeps a row in LDS.
+    expect(L.sf_frame_plan_create(64, 64, 32, 10, 120, 1, 4 | 2, None, ct.byref(plan)), 1, "exclude")
+    expect(L.sf_frame_plan_create(64, 5000, 32, 10, 120, 1, 4, None, ct.byref(plan)), 2, "4096")
+    expect(L.sf_frame_plan_create(64, 64, 32, 10, 120, 1, 64, None, ct.byref(plan)), 1, "unknown flags")
