@@ -95,6 +95,16 @@ int sf_sgm_set_epilogue(int mode);
 int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
                      uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
                      void *stream);
+/* Intensity-adaptive variant of the cited SGM method: the large-jump penalty at
+ * p is taken from the base image along the path,
+ *   P2(p, r) = P2                          if g = |I(p) - I(p - r)| = 0
+ *            = max(P1, floor(P2 / g))      otherwise,
+ * in place of the constant P2 (path starts have no predecessor and Lr = C).
+ *   img [H][pitch] uint8, the base image of the cost volume (pitch >= W,
+ *   H * pitch < 2^31); other arguments, limits and errors as sf_sgm_aggregate. */
+int sf_sgm_aggregate_adaptive(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W,
+                              int D, int P1, int P2, uint32_t path_mask, uint16_t *S,
+                              void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Winner-take-all, sub-pixel refinement, left-right check (Sec. 3.1: the
@@ -211,13 +221,17 @@ int sf_plan_destroy(sf_plan plan);
  *          diagonal search in the left volumes (sf_wta_right_diag), so the
  *          right-view aggregations are skipped (not with LEARNED; W <= 4096);
  *          SF_FRAME_MEDIAN = each left map's sub-pixel disparities pass the
- *          3x3 median (sf_median3x3) before the mask is applied.
+ *          3x3 median (sf_median3x3) before the mask is applied;
+ *          SF_FRAME_ADAPTIVE_P2 = intensity-adaptive large-jump penalty in
+ *          every aggregation (sf_sgm_aggregate_adaptive; each view's base
+ *          image: L0, R0, L1, R1).
  * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (device table upload). */
 #define SF_FRAME_PERSISTENT 1
 #define SF_FRAME_LEARNED 2
 #define SF_FRAME_DIAG 4
 #define SF_FRAME_MEDIAN 8
+#define SF_FRAME_ADAPTIVE_P2 16
 int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
                          const sf_agg_tuning *tuning /* host, NULL = default */, sf_plan *plan);
 /* L0, R0, L1, R1 [H][pitch] uint8; flow [H][W][2]; cam host pointer or NULL.

@@ -77,6 +77,7 @@ SIGNATURES = {
     "sf_prof_enable": (I, [I]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),
+    "sf_sgm_aggregate_adaptive": (I, [P, P, I, I, I, I, I, I, U32, P, P, SZ, P]),
     "sf_wta_right_diag": (I, [P, I, I, I, P, P]),
     "sf_lr_check": (I, [P, P, P, I, I, I, P, P, P]),
     "sf_median3x3": (I, [P, P, I, I, P, P]),

@@ -161,6 +161,21 @@ class Plan:
             pass
 
 
+def sgm_aggregate_adaptive(cost_vol, img, P1: int, P2: int, path_mask: int = 0xFF, out=None,
+                           workspace=None, stream=None):
+    """S with the intensity-adaptive large-jump penalty (img = the base image)."""
+    H, W, D = cost_vol.shape
+    if out is None:
+        out = torch.empty((H, W, D), dtype=torch.int16, device=cost_vol.device)
+    if workspace is None:
+        workspace = torch.empty(sgm_workspace_bytes(H, W, D), dtype=torch.uint8,
+                                device=cost_vol.device)
+    check(lib().sf_sgm_aggregate_adaptive(_ptr(cost_vol), _ptr(img), img.stride(0), H, W, D, P1,
+                                          P2, path_mask, _ptr(out), _ptr(workspace),
+                                          workspace.numel(), _stream(stream)))
+    return out
+
+
 def wta_right_diag(S_left, out=None, stream=None):
     """Right-view d* by the diagonal search in the left volume (no right aggregation)."""
     H, W, D = S_left.shape
@@ -190,18 +205,19 @@ def median3x3(m, mask=None, out=None, stream=None):
     return out
 
 
-FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN = 1, 2, 4, 8
+FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN, FRAME_ADAPTIVE_P2 = 1, 2, 4, 8, 16
 
 
 def frame_plan(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
                persistent: bool = False, learned: bool = False, tuning=None, diag: bool = False,
-               median: bool = False) -> Plan:
+               median: bool = False, adaptive_p2: bool = False) -> Plan:
     """tuning: an _lib.SfAggTuning for the aggregation launch (None = default).
     diag: right maps by the diagonal search (plain frames); median: 3x3 median of
     the left sub-pixel maps before the mask."""
     h = ct.c_void_p()
     flags = ((FRAME_PERSISTENT if persistent else 0) | (FRAME_LEARNED if learned else 0) |
-             (FRAME_DIAG if diag else 0) | (FRAME_MEDIAN if median else 0))
+             (FRAME_DIAG if diag else 0) | (FRAME_MEDIAN if median else 0) |
+             (FRAME_ADAPTIVE_P2 if adaptive_p2 else 0))
     tp = ct.byref(tuning) if tuning is not None else None
     check(lib().sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, tp, ct.byref(h)))
     return Plan(h)

@@ -63,7 +63,8 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_frame_plan_create: lr_tol < 0");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED,
                "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
-    SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED | SF_FRAME_DIAG | SF_FRAME_MEDIAN)) == 0,
+    SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED | SF_FRAME_DIAG | SF_FRAME_MEDIAN |
+                          SF_FRAME_ADAPTIVE_P2)) == 0,
                SF_EINVAL, "sf_frame_plan_create: unknown flags");
     SF_REQUIRE(!((flags & SF_FRAME_DIAG) && (flags & SF_FRAME_LEARNED)), SF_EINVAL,
                "sf_frame_plan_create: SF_FRAME_DIAG and SF_FRAME_LEARNED exclude each other");
@@ -86,6 +87,7 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     p->learned = (flags & SF_FRAME_LEARNED) != 0;
     p->diag = (flags & SF_FRAME_DIAG) != 0;
     p->median = (flags & SF_FRAME_MEDIAN) != 0;
+    p->adaptive = (flags & SF_FRAME_ADAPTIVE_P2) != 0;
     p->H = H;
     p->W = W;
     p->D = D;
@@ -167,6 +169,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     SF_REQUIRE(L0 && R0 && L1 && R1 && flow && disp0 && valid0 && disp1 && valid1 && sf4 && valid,
                SF_EINVAL, "sf_frame_run: NULL pointer");
     SF_REQUIRE(pitch >= p->W, SF_EINVAL, "sf_frame_run: pitch < W");
+    SF_REQUIRE((long long)p->H * pitch <= 0x7FFFFFFFLL, SF_EINVAL, "sf_frame_run: H * pitch too large");
     SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL, "sf_frame_run: camera given without xyz0/motion");
     if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_frame_run: focal length is zero");
     SF_REQUIRE(workspace, SF_EINVAL, "sf_frame_run: NULL workspace");
@@ -209,9 +212,14 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
         }
         co.n = 2; co.H = H; co.W = W; co.D = D;
         if ((rc = launch_cost(co, st))) return rc;
+        AggImages ims{};
+        if (p->adaptive) {
+            ims.n = 2;
+            for (int t = 0; t < 2; ++t) { ims.img[t] = img[2 * t]; ims.pitch[t] = pitch; }
+        }
         if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
                                    p->persistent_blocks, st, p->tuning.chains_per_block,
-                                   p->tuning.prefetch)))
+                                   p->tuning.prefetch, &ims)))
             return rc;
         WtaArgs wd{};
         for (int t = 0; t < 2; ++t) {
@@ -237,9 +245,15 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
         co.n = 4; co.H = H; co.W = W; co.D = D;
         if ((rc = launch_cost(co, st))) return rc;
 
+        // Each view's base image: L0, R0, L1, R1.
+        AggImages ims{};
+        if (p->adaptive) {
+            ims.n = 4;
+            for (int i = 0; i < 4; ++i) { ims.img[i] = img[i]; ims.pitch[i] = pitch; }
+        }
         if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
                                    p->persistent_blocks, st, p->tuning.chains_per_block,
-                                   p->tuning.prefetch)))
+                                   p->tuning.prefetch, &ims)))
             return rc;
 
         WtaArgs wr{};
@@ -289,6 +303,8 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
                    sf4 && valid,
                SF_EINVAL, "sf_frame_run_learned: NULL pointer");
     SF_REQUIRE(pitch >= p->W, SF_EINVAL, "sf_frame_run_learned: pitch < W");
+    SF_REQUIRE((long long)p->H * pitch <= 0x7FFFFFFFLL, SF_EINVAL,
+               "sf_frame_run_learned: H * pitch too large");
     SF_REQUIRE(!cam || (xyz0 && motion), SF_EINVAL,
                "sf_frame_run_learned: camera given without xyz0/motion");
     if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_frame_run_learned: focal length is zero");
@@ -316,9 +332,14 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     }
     co.n = 2; co.H = H; co.W = W; co.D = D;
     if ((rc = launch_cost(co, st))) return rc;
+    AggImages ims{};
+    if (p->adaptive) {
+        ims.n = 2;
+        for (int t = 0; t < 2; ++t) { ims.img[t] = img[2 * t]; ims.pitch[t] = pitch; }
+    }
     if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
-                               p->persistent_blocks, st,
-                          p->tuning.chains_per_block, p->tuning.prefetch)))
+                               p->persistent_blocks, st, p->tuning.chains_per_block,
+                               p->tuning.prefetch, &ims)))
         return rc;
     // WTA + sub-pixel + features of both left maps (no right view).
     float *feat = reinterpret_cast<float *>(at(p->off_feat));

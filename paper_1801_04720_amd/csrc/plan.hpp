@@ -20,7 +20,7 @@ struct Plan {
     // Frame workspace layout (byte offsets).
     size_t off_cen[4] = {}, off_cost[4] = {}, off_slab[4] = {}, off_wtar[2] = {}, off_wtal[2] = {};
     // Learned frame: features [2][H][W][4], sub-pixel maps, logits, scratch masks, net workspace.
-    bool learned = false, diag = false, median = false;
+    bool learned = false, diag = false, median = false, adaptive = false;
     size_t off_feat = 0, off_dsub[2] = {}, off_logit = 0, off_vtmp[2] = {}, off_lrws = 0;
     // Aggregation task table (plan-owned device memory).
     void *d_tables = nullptr;

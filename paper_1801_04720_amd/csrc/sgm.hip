@@ -22,6 +22,12 @@
 //     into a zeroed S with packed 32-bit atomics (each u16 half stays below
 //     8 (62 + P2) < 2^16, so no carry crosses halves).
 //
+//   * intensity-adaptive P2 (a variant of the cited method): the chain also
+//     streams its base-image bytes I(p) (prefetched with the costs) and uses
+//     max(P1, floor(P2 / |I(p) - I(p - r)|)) at each step (P2 where the step is
+//     flat); the quotient is a float reciprocal product corrected by one
+//     integer step either way, which is exact for P2 <= 8000, g <= 255.
+//
 // Two launch shapes share the chain code:
 //   * sgm_paths_kernel: one view, the block index enumerates its chains;
 //   * sgm_tasks_kernel: many views (the four of a scene-flow frame, or a batch
@@ -250,10 +256,11 @@ constexpr int SGM_U = 8;
 // Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
 // cost: [H][W][D]; slab: this direction's [H][W][D] u8 slab (ATOMIC == false)
 // or S [H][W][D] u16 (ATOMIC == true).
-template <int K, bool ATOMIC, int U = SGM_U>
+template <int K, bool ATOMIC, int U = SGM_U, bool ADAPT = false>
 __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
                                           uint16_t *__restrict__ S, int H, int W, int P1, int P2,
-                                          int r, int l, int j)
+                                          int r, int l, int j, const uint8_t *img = nullptr,
+                                          int pitch = 0)
 {
     constexpr int D = 16 * K;
     constexpr int NP = K / 2;
@@ -271,6 +278,14 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
         ATOMIC ? (void *)S : (void *)slab, (short)0, (int)((size_t)H * W * D), SGM_RSRC_WORD3);
     uint32_t st = (uint32_t)b0;                                  // next slab store (offset)
     uint16_t *stS = ATOMIC ? S + b0 : nullptr;                   // next S update
+    // Base image along the chain (adaptive P2 only), same out-of-range rule.
+    const __amdgpu_buffer_rsrc_t rs_img = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint8_t *>(ADAPT ? img : cost), (short)0, ADAPT ? (int)((size_t)H * pitch) : 0,
+        SGM_RSRC_WORD3);
+    uint32_t ild = ADAPT ? (uint32_t)(y * pitch + x) : 0u;
+    const uint32_t istep = ADAPT ? (uint32_t)(ry * pitch + rx) : 0u;
+    const float fP2 = (float)P2;
+    uint32_t prevI = 0;
 
     const u16x2 vP1 = (u16x2)((unsigned short)P1);
     // Path start: with Lr(p - r, .) = 0 and M = 0 the recurrence gives exactly
@@ -285,21 +300,41 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     uint32_t below = SGM_SENT, above = SGM_SENT;
     // Steps past the end of this chain (other chains of the wave may be longer)
     // load whatever the buffer holds there (zeros beyond it) and store nothing.
-    auto fetch = [&](int t0, CostRaw<K>(&buf)[U]) {
+    auto fetch = [&](int t0, CostRaw<K>(&buf)[U], uint32_t(&ib)[U]) {
         (void)t0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             load_raw_buf<K>(rs, ld, buf[u]);
             ld += (uint32_t)bstep;
+            if constexpr (ADAPT) {
+                ib[u] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs_img, (int)ild, 0, 0);
+                ild += istep;
+            } else {
+                ib[u] = 0;
+            }
         }
     };
-    auto step = [&](int t, const CostRaw<K> &raw) {
+    auto step = [&](int t, const CostRaw<K> &raw, uint32_t inten) {
         uint32_t c[NP];
         unpack<K>(raw, c);
         below = dpp_fill<DPP_ROW_SHR1>(below, L[NP - 1]);
         above = dpp_fill<DPP_ROW_SHL1>(above, L[0]);
+        uint32_t p2 = (uint32_t)P2;
+        if constexpr (ADAPT) {
+            // At the path start (L = 0, M = 0) any penalty gives Lr = C, so the
+            // first step needs no predecessor intensity.
+            const int gd = (int)inten - (int)prevI;
+            const int g = gd < 0 ? -gd : gd;
+            prevI = inten;
+            const int g1 = g > 0 ? g : 1;
+            int q = (int)(fP2 * __builtin_amdgcn_rcpf((float)g1));
+            const int rem = P2 - q * g1;
+            q += (rem >= g1 ? 1 : 0) - (rem < 0 ? 1 : 0);
+            p2 = g == 0 ? (uint32_t)P2 : (uint32_t)(q > P1 ? q : P1);
+        }
+        (void)inten;
         const u16x2 vM = (u16x2)((unsigned short)M);
-        const u16x2 vMP2 = (u16x2)((unsigned short)(M + P2));
+        const u16x2 vMP2 = (u16x2)((unsigned short)(M + p2));
         uint32_t nL[NP];
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
@@ -335,23 +370,26 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     };
 
     CostRaw<K> bufA[U], bufB[U];
-    fetch(0, bufA);
+    uint32_t ibA[U], ibB[U];
+    fetch(0, bufA, ibA);
     for (int t0 = 0; t0 < len; t0 += 2 * U) {
-        fetch(t0 + U, bufB);
+        fetch(t0 + U, bufB, ibB);
 #pragma unroll
-        for (int u = 0; u < U; ++u) step(t0 + u, bufA[u]);
-        fetch(t0 + 2 * U, bufA);
+        for (int u = 0; u < U; ++u) step(t0 + u, bufA[u], ibA[u]);
+        fetch(t0 + 2 * U, bufA, ibA);
 #pragma unroll
-        for (int u = 0; u < U; ++u) step(t0 + U + u, bufB[u]);
+        for (int u = 0; u < U; ++u) step(t0 + U + u, bufB[u], ibB[u]);
     }
+    (void)fP2;
 }
 
 // One view; block b, row q -> chain g = 16 b + q, mapped through the table.
-template <int K, bool ATOMIC>
+template <int K, bool ATOMIC, bool ADAPT>
 __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__restrict__ cost,
                                                            int H, int W, int P1, int P2,
                                                            PathTable tab, uint8_t *__restrict__ slab,
-                                                           uint16_t *__restrict__ S)
+                                                           uint16_t *__restrict__ S,
+                                                           const uint8_t *__restrict__ img, int pitch)
 {
     constexpr int D = 16 * K;
     const int g = blockIdx.x * SGM_CPB + (threadIdx.x >> 4);
@@ -361,18 +399,19 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
     while (g >= tab.off[k + 1]) ++k;
     const size_t npx = (size_t)H * W;
     uint8_t *sl = ATOMIC ? nullptr : slab + (size_t)k * npx * D;
-    sgm_chain<K, ATOMIC>(cost, sl, S, H, W, P1, P2, tab.dir[k], g - tab.off[k], j);
+    sgm_chain<K, ATOMIC, SGM_U, ADAPT>(cost, sl, S, H, W, P1, P2, tab.dir[k], g - tab.off[k], j, img,
+                                       pitch);
 }
 
 // Many views from a task table (all tasks of one launch share K = D / 16).
 // A block of 16 * c threads runs one task of up to c chains.  persistent:
 // gridDim.x blocks pull task indices from *counter (zeroed before the launch)
 // until the table is done; otherwise block b runs task b.
-template <int K, int U>
+template <int K, int U, bool ADAPT>
 __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
                                                            const AggTask *__restrict__ tasks,
                                                            int ntasks, uint8_t *base,
-                                                           int *counter)
+                                                           int *counter, AggImages ims)
 {
     __shared__ int s_task;
     const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
@@ -391,8 +430,10 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
             const uint8_t *cost = reinterpret_cast<const uint8_t *>((uintptr_t)base + v.cost_off);
             uint8_t *slab = reinterpret_cast<uint8_t *>((uintptr_t)base + v.slab_off) +
                             (size_t)tk.slot * v.H * v.W * (16 * K);
-            sgm_chain<K, false, U>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
-                                   tk.line0 + q, j);
+            const uint8_t *img = ADAPT ? ims.img[tk.view] : nullptr;
+            const int pitch = ADAPT ? ims.pitch[tk.view] : 0;
+            sgm_chain<K, false, U, ADAPT>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
+                                          tk.line0 + q, j, img, pitch);
         }
         if (!counter) return;
     }
@@ -440,14 +481,24 @@ static int g_epilogue_mode = 0;
 
 template <int K>
 static void launch_paths(bool atomic, int nblk, hipStream_t st, const uint8_t *cost, int H, int W,
-                         int P1, int P2, const PathTable &tab, uint8_t *slab, uint16_t *S)
+                         int P1, int P2, const PathTable &tab, uint8_t *slab, uint16_t *S,
+                         const uint8_t *img, int pitch)
 {
-    if (atomic)
-        hipLaunchKernelGGL((sgm_paths_kernel<K, true>), dim3(nblk), dim3(SGM_NT), 0, st, cost, H,
-                           W, P1, P2, tab, slab, S);
-    else
-        hipLaunchKernelGGL((sgm_paths_kernel<K, false>), dim3(nblk), dim3(SGM_NT), 0, st, cost,
-                           H, W, P1, P2, tab, slab, S);
+    if (img) {
+        if (atomic)
+            hipLaunchKernelGGL((sgm_paths_kernel<K, true, true>), dim3(nblk), dim3(SGM_NT), 0, st,
+                               cost, H, W, P1, P2, tab, slab, S, img, pitch);
+        else
+            hipLaunchKernelGGL((sgm_paths_kernel<K, false, true>), dim3(nblk), dim3(SGM_NT), 0, st,
+                               cost, H, W, P1, P2, tab, slab, S, img, pitch);
+    } else {
+        if (atomic)
+            hipLaunchKernelGGL((sgm_paths_kernel<K, true, false>), dim3(nblk), dim3(SGM_NT), 0, st,
+                               cost, H, W, P1, P2, tab, slab, S, img, pitch);
+        else
+            hipLaunchKernelGGL((sgm_paths_kernel<K, false, false>), dim3(nblk), dim3(SGM_NT), 0, st,
+                               cost, H, W, P1, P2, tab, slab, S, img, pitch);
+    }
 }
 
 // --- task tables (host) ------------------------------------------------------
@@ -503,18 +554,34 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
 
 template <int K>
 static void launch_tasks_k(int U, int nb, int nthr, hipStream_t st, const AggView *v,
-                           const AggTask *t, int n, uint8_t *base, int *counter)
+                           const AggTask *t, int n, uint8_t *base, int *counter, const AggImages &ims)
 {
-    if (U == 4)
-        hipLaunchKernelGGL((sgm_tasks_kernel<K, 4>), dim3(nb), dim3(nthr), 0, st, v, t, n, base, counter);
-    else
-        hipLaunchKernelGGL((sgm_tasks_kernel<K, 8>), dim3(nb), dim3(nthr), 0, st, v, t, n, base, counter);
+    if (ims.n > 0) {
+        if (U == 4)
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, true>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+                               base, counter, ims);
+        else
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, true>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+                               base, counter, ims);
+    } else {
+        if (U == 4)
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, false>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+                               base, counter, ims);
+        else
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, false>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+                               base, counter, ims);
+    }
 }
 
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
                      uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
-                     int chains_per_block, int prefetch)
+                     int chains_per_block, int prefetch, const AggImages *images)
 {
+    AggImages ims{};
+    if (images) ims = *images;
+    if (ims.n < 0 || ims.n > AGG_MAX_IMG) return fail(SF_EINVAL, "launch_agg_tasks: bad image count");
+    for (int i = 0; i < ims.n; ++i)
+        if (!ims.img[i]) return fail(SF_EINVAL, "launch_agg_tasks: NULL base image");
     if (ntasks <= 0) return SF_OK;
     if (chains_per_block != 4 && chains_per_block != 8 && chains_per_block != 16)
         return fail(SF_EINVAL, "launch_agg_tasks: chains per block must be 4, 8 or 16");
@@ -530,14 +597,14 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
     }
     const int nthr = 16 * chains_per_block;
     switch (K) {
-    case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 4: launch_tasks_k<4>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 6: launch_tasks_k<6>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 8: launch_tasks_k<8>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 10: launch_tasks_k<10>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 12: launch_tasks_k<12>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 14: launch_tasks_k<14>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
-    case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter); break;
+    case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 4: launch_tasks_k<4>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 6: launch_tasks_k<6>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 8: launch_tasks_k<8>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 10: launch_tasks_k<10>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 12: launch_tasks_k<12>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 14: launch_tasks_k<14>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
     default: return fail(SF_EUNSUPPORTED, "launch_agg_tasks: unsupported K");
     }
     return launch_status("sgm_tasks_kernel");
@@ -560,11 +627,10 @@ extern "C" size_t sf_sgm_workspace_bytes(int H, int W, int D)
     return (size_t)8 * H * W * D;
 }
 
-extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
-                                uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
-                                void *stream)
+static int aggregate_impl(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W, int D,
+                          int P1, int P2, uint32_t path_mask, uint16_t *S, void *workspace,
+                          size_t ws_bytes, void *stream)
 {
-    clear_error();
     SF_REQUIRE(cost && S, SF_EINVAL, "sf_sgm_aggregate: NULL pointer");
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_sgm_aggregate: H and W must be positive");
     SF_REQUIRE(P1 >= 0 && P2 >= P1, SF_EINVAL, "sf_sgm_aggregate: need 0 <= P1 <= P2");
@@ -605,14 +671,14 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     {
         ProfScope prof("sgm_paths", st);
         switch (D / 16) {
-        case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 6: launch_paths<6>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 8: launch_paths<8>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 10: launch_paths<10>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 12: launch_paths<12>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 14: launch_paths<14>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
-        case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S); break;
+        case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 4: launch_paths<4>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 6: launch_paths<6>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 8: launch_paths<8>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 10: launch_paths<10>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 12: launch_paths<12>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 14: launch_paths<14>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
+        case 16: launch_paths<16>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
         default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
         }
     }
@@ -633,4 +699,23 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
     default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate: unsupported D");
     }
     return launch_status("slab_sum_kernel");
+}
+
+extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
+                                uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
+                                void *stream)
+{
+    clear_error();
+    return aggregate_impl(cost, nullptr, 0, H, W, D, P1, P2, path_mask, S, workspace, ws_bytes, stream);
+}
+
+extern "C" int sf_sgm_aggregate_adaptive(const uint8_t *cost, const uint8_t *img, int pitch, int H,
+                                         int W, int D, int P1, int P2, uint32_t path_mask,
+                                         uint16_t *S, void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(img, SF_EINVAL, "sf_sgm_aggregate_adaptive: NULL image");
+    SF_REQUIRE(pitch >= W, SF_EINVAL, "sf_sgm_aggregate_adaptive: pitch < W");
+    SF_REQUIRE((long long)H * pitch <= 0x7FFFFFFFLL, SF_EINVAL, "sf_sgm_aggregate_adaptive: image too large");
+    return aggregate_impl(cost, img, pitch, H, W, D, P1, P2, path_mask, S, workspace, ws_bytes, stream);
 }

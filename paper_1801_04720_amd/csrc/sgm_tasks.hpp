@@ -26,6 +26,15 @@ struct AggTask {
     int view, slot, line0, nlines;
 };
 
+// Base images of the views of a launch, for the intensity-adaptive large-jump
+// penalty (n = 0: constant P2).  img[v] is view v's base image [H][pitch[v]].
+constexpr int AGG_MAX_IMG = 8;
+struct AggImages {
+    const uint8_t *img[AGG_MAX_IMG];
+    int pitch[AGG_MAX_IMG];
+    int n;
+};
+
 int chains_of(int r, int H, int W);
 void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, int view,
                       const AggView &v, int chains_per_task = 16);
@@ -34,8 +43,10 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
 // *d_counter (reset on the stream first); 0: one block per task.
 // chains_per_block in {4, 8, 16} must match the table's chains per task;
 // prefetch (cost steps in flight per chain) in {4, 8}.
+// images: NULL or n = 0 for the constant P2; otherwise every view index of the
+// table must be < n.
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
                      uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
-                     int chains_per_block = 16, int prefetch = 8);
+                     int chains_per_block = 16, int prefetch = 8, const AggImages *images = nullptr);
 
 }  // namespace sf

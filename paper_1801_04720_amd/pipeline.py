@@ -20,9 +20,9 @@ class PlainFrame:
 
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
                  cam=(721.5, 0.54, None, None), path_mask: int = 0xFF, device="cuda:0",
-                 diag: bool = False, median: bool = False):
+                 diag: bool = False, median: bool = False, adaptive_p2: bool = False):
         self.H, self.W, self.D = H, W, D
-        self.diag, self.median = diag, median
+        self.diag, self.median, self.adaptive = diag, median, adaptive_p2
         self.P1, self.P2, self.tol, self.mask = P1, P2, lr_tol, path_mask
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
@@ -43,16 +43,22 @@ class PlainFrame:
         self.dense = e(H, W, dt=torch.float32)
         self.ones = e(H, W, dt=torch.uint8)
 
+    def _aggregate(self, base_img, out):
+        if self.adaptive:
+            api.sgm_aggregate_adaptive(self.cost, base_img, self.P1, self.P2, self.mask, out=out,
+                                       workspace=self.ws)
+        else:
+            api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=out, workspace=self.ws)
+
     def disparity(self, t: int, left, right, cen_l, cen_r):
         api.census(left, out=cen_l)
         api.census(right, out=cen_r)
         m = self.maps[t]
         if not self.diag:
             api.cost(cen_r, cen_l, self.D, True, out=self.cost)
-            api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_right,
-                              workspace=self.ws)
+            self._aggregate(right, self.S_right)
         api.cost(cen_l, cen_r, self.D, False, out=self.cost)
-        api.sgm_aggregate(self.cost, self.P1, self.P2, self.mask, out=self.S_left, workspace=self.ws)
+        self._aggregate(left, self.S_left)
         if not self.diag and not self.median:
             return api.wta_lr(self.S_left, self.S_right, None, self.P2, self.tol, out=m)
         # Left WTA without a check (dense sub-pixel map), the right map, then the mask.
@@ -84,14 +90,15 @@ class FusedFrame:
 
     def __init__(self, H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
                  cam=(721.5, 0.54, None, None), persistent: bool = False, learned_params=None,
-                 tuning=None, device="cuda:0", diag: bool = False, median: bool = False):
+                 tuning=None, device="cuda:0", diag: bool = False, median: bool = False,
+                 adaptive_p2: bool = False):
         self.H, self.W, self.D = H, W, D
         f, B, cx, cy = cam
         self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
         self.params = learned_params
         self.plan = api.frame_plan(H, W, D, P1, P2, lr_tol, persistent,
                                    learned=learned_params is not None, tuning=tuning, diag=diag,
-                                   median=median)
+                                   median=median, adaptive_p2=adaptive_p2)
         dev = torch.device(device)
         e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
         self.ws = e(self.plan.workspace_bytes(), dt=torch.uint8)

@@ -150,3 +150,110 @@ def test_diag_right_map_matches_right_pass_without_smoothing(orc):
     wd = host(api.wta_right_diag(Sl))
     W = p.left.shape[1]
     assert np.array_equal(wd[:, :W - D + 1], wr[:, :W - D + 1])
+
+
+# --- intensity-adaptive P2 ---------------------------------------------------------------------
+
+def adaptive_image(rng, H, W, pitch):
+    # Flat patches (g = 0), unit steps and strong edges.
+    base = rng.choice(np.array([0, 1, 3, 40, 200], np.int64), (H // 3 + 1, W // 3 + 1))
+    img = np.kron(base, np.ones((3, 3), np.int64))[:H, :W]
+    img = (img + rng.integers(0, 2, (H, W))) % 256
+    wide = np.zeros((H, pitch), np.uint8)
+    wide[:, :W] = img
+    wide[:, W:] = 255
+    return wide
+
+
+@pytest.mark.parametrize("H,W,D", [(1, 1, 32), (5, 37, 32), (21, 37, 64), (9, 70, 128), (6, 45, 256)])
+@pytest.mark.parametrize("P1,P2", [(10, 120), (7, 40), (5, 300)])
+def test_aggregate_adaptive_vs_oracle(orc, H, W, D, P1, P2):
+    say("aggregate adaptive", H, W, D, P1, P2)
+    rng = np.random.default_rng(H * 31 + W + D + P2)
+    C = rng.integers(0, 63, (H, W, D)).astype(np.uint8)
+    wide = adaptive_image(rng, H, W, W + 5)
+    got = host(api.sgm_aggregate_adaptive(dev(C), dev(wide), P1, P2), np.uint16)
+    assert np.array_equal(got, orc.aggregate_adaptive(C, np.ascontiguousarray(wide[:, :W]), P1, P2))
+
+
+def test_aggregate_adaptive_pitch_and_masks(orc):
+    import ctypes as ct
+
+    from paper_1801_04720_amd import _lib
+
+    say("aggregate adaptive pitch / masks")
+    rng = np.random.default_rng(91)
+    H, W, D, pitch = 23, 41, 64, 64
+    C = rng.integers(0, 63, (H, W, D)).astype(np.uint8)
+    wide = adaptive_image(rng, H, W, pitch)
+    img_t = dev(wide)  # [H][pitch]; the entry point reads only the first W bytes of each row
+    for mask in (0x01, 0x0C, 0x30, 0xC0, 0xFF):
+        S = torch.empty((H, W, D), dtype=torch.int16, device=DEV)
+        ws = torch.empty(api.sgm_workspace_bytes(H, W, D), dtype=torch.uint8, device=DEV)
+        Ct = dev(C)
+        _lib.check(_lib.lib().sf_sgm_aggregate_adaptive(
+            ct.c_void_p(Ct.data_ptr()), ct.c_void_p(img_t.data_ptr()), pitch, H, W, D, 10, 120, mask,
+            ct.c_void_p(S.data_ptr()), ct.c_void_p(ws.data_ptr()), ws.numel(),
+            ct.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        exp = orc.aggregate_adaptive(C, np.ascontiguousarray(wide[:, :W]), 10, 120, mask)
+        assert np.array_equal(host(S, np.uint16), exp), mask
+
+
+AVARIANTS = [(False, False), (True, False), (False, True)]  # (diag, median) with adaptive P2
+
+
+@pytest.mark.parametrize("diag,median", AVARIANTS)
+@pytest.mark.parametrize("H,W,D", [(48, 160, 32), (33, 300, 256)])
+def test_fused_frame_adaptive_small(orc, diag, median, H, W, D):
+    say("fused frame adaptive", diag, median, H, W, D)
+    fr = synth.frame_planar(synth.rng_for(8, D + 2 * H), H, W, D, 20.0)
+    ff = FusedFrame(H, W, D, diag=diag, median=median, adaptive_p2=True, device=DEV)
+    got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
+    torch.cuda.synchronize()
+    flags = orc.ADAPTIVE | (orc.DIAG if diag else 0) | (orc.MEDIAN if median else 0)
+    check_frame(got, oracle_frame_ex(orc, fr, D, ff.cam, flags))
+
+
+def test_fused_frame_adaptive_c2_vs_oracle(orc):
+    say("fused frame adaptive 1242x375 D=128")
+    fr = synth.frame_c2(5)
+    ff = FusedFrame(375, 1242, 128, adaptive_p2=True, device=DEV)
+    got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
+    torch.cuda.synchronize()
+    check_frame(got, oracle_frame_ex(orc, fr, 128, ff.cam, orc.ADAPTIVE))
+
+
+@pytest.mark.parametrize("diag", [False, True])
+def test_fused_equals_stagewise_adaptive(diag):
+    say("fused vs per-stage adaptive", diag)
+    fr = synth.frame_c2(6)
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    a = FusedFrame(375, 1242, 128, diag=diag, adaptive_p2=True, device=DEV).run(*args)
+    a = {k: host(v).copy() for k, v in a.items()}
+    m0, m1, c = PlainFrame(375, 1242, 128, diag=diag, adaptive_p2=True, device=DEV).run(*args)
+    torch.cuda.synchronize()
+    assert np.array_equal(a["valid0"], host(m0["valid"]))
+    assert np.array_equal(a["disp1"], host(m1["disp"]))
+    for k in ("sf4", "valid", "xyz0", "motion"):
+        assert np.array_equal(a[k], host(c[k]), equal_nan=True), k
+
+
+def test_learned_frame_adaptive_equals_stagewise():
+    from paper_1801_04720_amd import lrnet
+
+    say("learned frame adaptive vs stages")
+    H, W, D = 64, 200, 64
+    fr = synth.frame_planar(synth.rng_for(8, 17), H, W, D, 25.0)
+    prm = dev(lrnet.init_params(9))
+    args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
+    got = FusedFrame(H, W, D, learned_params=prm, adaptive_p2=True, device=DEV).run(*args)
+    got = {k: host(v).copy() for k, v in got.items()}
+    for t, key in ((0, "0"), (1, "1")):
+        L, R = args[2 * t], args[2 * t + 1]
+        Sl = api.sgm_aggregate_adaptive(api.cost(api.census(L), api.census(R), D, False), L, 10, 120)
+        m = api.wta_lr(Sl, None, L, 120, 1, want_feat=True)
+        logits = lrnet.forward(prm, m["feat"][None].contiguous())
+        valid, disp = lrnet.mask(logits[0], m["wta_left"], m["disp"])
+        torch.cuda.synchronize()
+        assert np.array_equal(got["valid" + key], host(valid))
+        assert np.array_equal(got["disp" + key], host(disp))
