@@ -363,45 +363,65 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
             "sceneflow_density_learned": both(out["valid"])}
 
 
-def diag_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
-    """Plain frame whose right maps come from the diagonal search in the left
-    volumes (right-view aggregations skipped): fps, speed-up over the full plain
-    frame, agreement of its masks with the full LR check, and its kernel times."""
+def variants_leg(args, plain_pipe, inputs, gt0, H, W, D, ms_plain, dev):
+    """Frames with the cited SGM method's variants: right maps by the diagonal
+    search in the left volumes (right-view aggregations skipped), 3x3 median of
+    the sub-pixel maps, intensity-adaptive P2, and all three.  Per variant: ms
+    per frame, speed-up over the full plain frame, agreement of the t0/t1 masks
+    with the plain LR check, and the t0 map's density and end-point error
+    against the generator's ground-truth disparity."""
     import torch
 
     from paper_1801_04720_amd import _lib
     from paper_1801_04720_amd.pipeline import FusedFrame
 
-    tuning = None
+    lib = _lib.lib()
+    t2 = t4 = None
     if not args.no_autotune:
         from paper_1801_04720_amd import batch
 
-        tuning, _ = batch.autotune(H, W, D, nviews=2,
-                                   cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
-    dp = FusedFrame(H, W, D, diag=True, tuning=tuning, device=dev)
-    for _ in range(args.warmup):
-        dp.run(*inputs)
-    torch.cuda.synchronize()
-    lib = _lib.lib()
-    _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = dp.run(*inputs)
-    torch.cuda.synchronize()
-    ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
-    lib.sf_prof_disable()
-    kern = {}
-    for name in ["cost", "sgm_tasks", "wta_diag"]:
-        tot, n = kernel_ms(lib, name)
-        if n:
-            kern[name] = tot / n
+        cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+        t2, _ = batch.autotune(H, W, D, nviews=2, cache=cache)
+        t4, _ = batch.autotune(H, W, D, nviews=4, cache=cache)
+    gt = torch.from_numpy(gt0).to(dev)
     plain = plain_pipe.run(*inputs)
-    torch.cuda.synchronize()
-    agree = [float((out[k] == plain[k]).float().mean().item()) for k in ("valid0", "valid1")]
-    return {"fps_diag": 1e3 / ms, "ms_diag": ms, "speedup_diag_vs_plain": ms_plain / ms,
-            "diag_mask_agreement_t0_t1": agree, "diag_kernels_avg_ms": kern,
-            "sceneflow_density_diag": float((out["valid"] & 1).float().mean().item())}
+    plain = {k: plain[k].clone() for k in ("valid0", "valid1", "disp0")}
+
+    def quality(o):
+        v = o["valid0"].bool()
+        return {"density_t0": float(v.float().mean().item()),
+                "epe_t0": float((o["disp0"][v] - gt[v]).abs().mean().item())}
+
+    res = {"plain": quality(plain)}
+    for name, kw in (("diag", dict(diag=True)), ("median", dict(median=True)),
+                     ("adaptive_p2", dict(adaptive_p2=True)),
+                     ("diag_median_adaptive", dict(diag=True, median=True, adaptive_p2=True))):
+        fp = FusedFrame(H, W, D, tuning=t2 if kw.get("diag") else t4, device=dev, **kw)
+        for _ in range(args.warmup):
+            fp.run(*inputs)
+        torch.cuda.synchronize()
+        _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = fp.run(*inputs)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / max(args.steps, 1)
+        lib.sf_prof_disable()
+        kern = {}
+        for kname in ["cost", "sgm_tasks", "wta_slab_right", "wta_slab_left", "wta_diag", "median3x3"]:
+            tot, n = kernel_ms(lib, kname)
+            if n:
+                kern[kname] = tot / n
+        r = {"ms": ms, "fps": 1e3 / ms, "speedup_vs_plain": ms_plain / ms,
+             "mask_agreement_t0_t1": [float((out[k] == plain[k]).float().mean().item())
+                                      for k in ("valid0", "valid1")],
+             "kernels_avg_ms": kern}
+        r.update(quality(out))
+        res[name] = r
+        del fp
+    return {"variants": res, "fps_diag": res["diag"]["fps"], "ms_diag": res["diag"]["ms"],
+            "speedup_diag_vs_plain": res["diag"]["speedup_vs_plain"]}
 
 
 def bench_peaks(args, dev):
@@ -456,8 +476,8 @@ def main():
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
-    ap.add_argument("--no-diag", action="store_true",
-                    help="skip the leg whose right maps come from the diagonal search")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the SGM-variant legs (diagonal search, median, adaptive P2)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default aggregation tuning instead of the autotuner's choice")
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
@@ -599,8 +619,8 @@ def main():
     }
     if not args.no_learned and args.pipeline != "stages":
         res.update(learned_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
-    if not args.no_diag and args.pipeline != "stages":
-        res.update(diag_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
+    if not args.no_variants and args.pipeline != "stages":
+        res.update(variants_leg(args, pipe, (L0, R0, L1, R1, flow), fr.t0.gt_disp, H, W, D, ms, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)
