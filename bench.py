@@ -363,16 +363,19 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
             "sceneflow_density_learned": both(out["valid"])}
 
 
-def variants_leg(args, plain_pipe, inputs, gt0, H, W, D, ms_plain, dev):
+def variants_leg(args, plain_pipe, inputs, fr, H, W, D, ms_plain, dev):
     """Frames with the cited SGM method's variants: right maps by the diagonal
     search in the left volumes (right-view aggregations skipped), 3x3 median of
     the sub-pixel maps, intensity-adaptive P2, and all three.  Per variant: ms
     per frame, speed-up over the full plain frame, agreement of the t0/t1 masks
-    with the plain LR check, and the t0 map's density and end-point error
-    against the generator's ground-truth disparity."""
+    with the plain LR check, the t0 map's density and end-point error against
+    the generator's ground-truth disparity, and the scene-flow outlier rates
+    (the paper's Table 1 metric) of the sparse map ("Est") and of its
+    densified version ("All")."""
     import torch
 
-    from paper_1801_04720_amd import _lib
+    from paper_1801_04720_amd import _lib, api
+    from paper_1801_04720_amd.evaluate import sf_outliers
     from paper_1801_04720_amd.pipeline import FusedFrame
 
     lib = _lib.lib()
@@ -383,16 +386,30 @@ def variants_leg(args, plain_pipe, inputs, gt0, H, W, D, ms_plain, dev):
         cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
         t2, _ = batch.autotune(H, W, D, nviews=2, cache=cache)
         t4, _ = batch.autotune(H, W, D, nviews=4, cache=cache)
-    gt = torch.from_numpy(gt0).to(dev)
+    gt = torch.from_numpy(fr.t0.gt_disp).to(dev)
     plain = plain_pipe.run(*inputs)
-    plain = {k: plain[k].clone() for k in ("valid0", "valid1", "disp0")}
+    plain = {k: plain[k].clone() for k in ("valid0", "valid1", "disp0", "sf4", "valid")}
 
     def quality(o):
         v = o["valid0"].bool()
+        dense = api.densify(o["sf4"], o["valid"])
+        gts = (fr.gt_flow, fr.t0.gt_disp, fr.gt_disp1_at_t0)
         return {"density_t0": float(v.float().mean().item()),
-                "epe_t0": float((o["disp0"][v] - gt[v]).abs().mean().item())}
+                "epe_t0": float((o["disp0"][v] - gt[v]).abs().mean().item()),
+                "sf_outliers_est": sf_outliers(o["sf4"], o["valid"] & 1, *gts),
+                "sf_outliers_all": sf_outliers(dense["sf4"], dense["fill"] > 0, *gts)}
 
     res = {"plain": quality(plain)}
+    # Densification of the plain frame's map, timed on its own.
+    dn = api.densify(plain["sf4"], plain["valid"])
+    torch.cuda.synchronize()
+    _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
+    for _ in range(args.steps):
+        api.densify(plain["sf4"], plain["valid"], out=dn)
+    torch.cuda.synchronize()
+    lib.sf_prof_disable()
+    tot, n = kernel_ms(lib, "densify")
+    res["plain"]["densify_ms"] = tot / max(n, 1)
     for name, kw in (("diag", dict(diag=True)), ("median", dict(median=True)),
                      ("adaptive_p2", dict(adaptive_p2=True)),
                      ("diag_median_adaptive", dict(diag=True, median=True, adaptive_p2=True))):
@@ -620,7 +637,7 @@ def main():
     if not args.no_learned and args.pipeline != "stages":
         res.update(learned_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
     if not args.no_variants and args.pipeline != "stages":
-        res.update(variants_leg(args, pipe, (L0, R0, L1, R1, flow), fr.t0.gt_disp, H, W, D, ms, dev))
+        res.update(variants_leg(args, pipe, (L0, R0, L1, R1, flow), fr, H, W, D, ms, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)

@@ -341,6 +341,25 @@ int sf_prof_disable(void);
 int sf_prof_query(const char *kernel, double *total_ms, int *launches);
 
 /* ---------------------------------------------------------------------------
+ * Densification of the sparse scene-flow map (the paper reports a dense
+ * version interpolated by the benchmark and names a better interpolation as
+ * future work, Sec. 4; the fill rule is this library's own):
+ *   - an undefined pixel takes all four values (u, v, d0, d1) of the nearest
+ *     defined pixel to its left or right in the same row; when both exist, the
+ *     one with the smaller d0 (the farther surface), ties to the left;
+ *   - a row with no defined pixel copies the nearest row that has one, pixel by
+ *     pixel (ties to the row above).
+ *   sf4 [H][W][4] float, valid [H][W] uint8 (bit 0 = defined), as sf_combine
+ *   writes them; out [H][W][4] float (output, distinct from sf4; both 16-byte
+ *   aligned); fill [H][W] uint8 (output): 1 defined, 2 filled from the row,
+ *   3 copied from another row, 0 (with NaNs) only when nothing is defined.
+ *   workspace: at least sf_densify_workspace_bytes(H) bytes of device scratch.
+ * Supported: W <= 8192.  Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_ENOMEM. */
+size_t sf_densify_workspace_bytes(int H);
+int sf_densify(const float *sf4, const uint8_t *valid, int H, int W, float *out, uint8_t *fill,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Machine-balance probes (not part of the method): the measured ceilings the
  * kernels' roofline fractions are also quoted against.
  *

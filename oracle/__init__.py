@@ -61,6 +61,7 @@ def _declare(L):
     L.oracle_wta_right_diag.argtypes = [P, I, I, I, P]
     L.oracle_median3x3.argtypes = [P, I, I, P]
     L.oracle_disparity_ex.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P, P, P]
+    L.oracle_densify.argtypes = [P, P, I, I, P, P]
     L.oracle_features.argtypes = [P, I, P, P, I, I, I, I, P]
     L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
     L.oracle_lrnet.restype = ct.c_double
@@ -209,6 +210,17 @@ def disparity(left, right, D, P1=10, P2=120, path_mask=0xFF, tol=1):
     lib().oracle_disparity(_p(L), _p(R), H, W, W, D, P1, P2, path_mask, tol, _p(w), _p(disp),
                            _p(valid))
     return w, disp, valid
+
+
+def densify(sf4, valid):
+    """Dense scene-flow map and fill code (1 defined, 2 row fill, 3 copied row, 0 none)."""
+    s = np.ascontiguousarray(sf4, np.float32)
+    v = np.ascontiguousarray(valid, np.uint8)
+    H, W = v.shape
+    out = np.zeros((H, W, 4), np.float32)
+    fill = np.zeros((H, W), np.uint8)
+    lib().oracle_densify(_p(s), _p(v), H, W, _p(out), _p(fill))
+    return out, fill
 
 
 DIAG, MEDIAN, ADAPTIVE = 1, 2, 4

@@ -457,3 +457,65 @@ void oracle_disparity_ex(const uint8_t *left, const uint8_t *right, int H, int W
     oracle_lr_check(wtaL, wtaR, dsubL, H, W, tol, valid, disp);
     free(cl); free(cr); free(cost); free(S); free(wtaR); free(dsubL); free(med);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Densification of the sparse scene-flow map (the paper reports a dense
+ * version interpolated by the benchmark and names a better interpolation as
+ * future work; this fill is defined here, not by the paper).
+ * Reading:
+ *   - an undefined pixel takes all four values (u, v, d0, d1) of the nearest
+ *     defined pixel to its left or to its right in the same row; when both
+ *     exist, the one with the smaller d0 (the farther surface: gaps come from
+ *     occlusions and the occluded surface is the background); ties go left;
+ *   - a row with no defined pixel copies, pixel by pixel, the row-filled values
+ *     of the nearest row that has a defined pixel (ties go to the row above);
+ *   - fill = 1 where the input was defined, 2 where filled from the row, 3 where
+ *     copied from another row, 0 (and four NaNs) if no pixel is defined at all.
+ * sf4 / out [H][W][4] float; valid [H][W] uint8 (bit 0 = defined). */
+void oracle_densify(const float *sf4, const uint8_t *valid, int H, int W, float *out, uint8_t *fill)
+{
+    const float nanv = nanf("");
+    int *rowok = (int *)calloc((size_t)H, sizeof(int));
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x)
+            if (valid[(size_t)y * W + x] & 1) rowok[y] = 1;
+        for (int x = 0; x < W; ++x) {
+            size_t i = (size_t)y * W + x;
+            int src = -1;
+            uint8_t f = 0;
+            if (valid[i] & 1) {
+                src = x;
+                f = 1;
+            } else if (rowok[y]) {
+                int xl = -1, xr = -1;
+                for (int k = x - 1; k >= 0; --k)
+                    if (valid[(size_t)y * W + k] & 1) { xl = k; break; }
+                for (int k = x + 1; k < W; ++k)
+                    if (valid[(size_t)y * W + k] & 1) { xr = k; break; }
+                if (xl >= 0 && xr >= 0)
+                    src = (sf4[((size_t)y * W + xr) * 4 + 2] < sf4[((size_t)y * W + xl) * 4 + 2]) ? xr : xl;
+                else
+                    src = xl >= 0 ? xl : xr;
+                f = 2;
+            }
+            for (int c = 0; c < 4; ++c)
+                out[i * 4 + c] = src >= 0 ? sf4[((size_t)y * W + src) * 4 + c] : nanv;
+            fill[i] = f;
+        }
+    }
+    for (int y = 0; y < H; ++y) {
+        if (rowok[y]) continue;
+        int best = -1;
+        for (int dy = 1; dy < H && best < 0; ++dy) {
+            if (y - dy >= 0 && rowok[y - dy]) best = y - dy;
+            else if (y + dy < H && rowok[y + dy]) best = y + dy;
+        }
+        if (best < 0) continue; /* nothing defined anywhere */
+        for (int x = 0; x < W; ++x) {
+            size_t i = (size_t)y * W + x, s = (size_t)best * W + x;
+            for (int c = 0; c < 4; ++c) out[i * 4 + c] = out[s * 4 + c];
+            fill[i] = 3;
+        }
+    }
+    free(rowok);
+}

@@ -81,6 +81,8 @@ SIGNATURES = {
     "sf_wta_right_diag": (I, [P, I, I, I, P, P]),
     "sf_lr_check": (I, [P, P, P, I, I, I, P, P, P]),
     "sf_median3x3": (I, [P, P, I, I, P, P]),
+    "sf_densify_workspace_bytes": (SZ, [I]),
+    "sf_densify": (I, [P, P, I, I, P, P, P, SZ, P]),
     "sf_probe_stream": (I, [P, P, SZ, I, P]),
     "sf_probe_pk_u16": (I, [P, I, I, P]),
 }

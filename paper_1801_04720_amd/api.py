@@ -205,6 +205,25 @@ def median3x3(m, mask=None, out=None, stream=None):
     return out
 
 
+def densify(sf4, valid, out=None, stream=None):
+    """Dense scene-flow map -> {"sf4": [H][W][4] float, "fill": [H][W] uint8}."""
+    H, W = valid.shape
+    dev = valid.device
+    o = out or {}
+    dense = o.get("sf4")
+    if dense is None:
+        dense = torch.empty((H, W, 4), dtype=torch.float32, device=dev)
+    fill = o.get("fill")
+    if fill is None:
+        fill = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    ws = o.get("workspace")
+    if ws is None:
+        ws = torch.empty(max(1, lib().sf_densify_workspace_bytes(H)), dtype=torch.uint8, device=dev)
+    check(lib().sf_densify(_ptr(sf4), _ptr(valid), H, W, _ptr(dense), _ptr(fill), _ptr(ws), ws.numel(),
+                           _stream(stream)))
+    return {"sf4": dense, "fill": fill}
+
+
 FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN, FRAME_ADAPTIVE_P2 = 1, 2, 4, 8, 16
 
 
