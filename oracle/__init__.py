@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg may import this package; the product path never does.  The
-C sources (sgm_oracle.c, lrnet_oracle.c) are plain single-threaded loops that
+C sources (sgm_oracle.c, lrnet_oracle.c, flow_oracle.c) are plain single-threaded loops that
 follow the definitions one by one; this module only marshals numpy arrays.
 """
 from __future__ import annotations
@@ -15,7 +15,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRCS = ["sgm_oracle.c", "lrnet_oracle.c"]
+_SRCS = ["sgm_oracle.c", "lrnet_oracle.c", "flow_oracle.c"]
 _lib = None
 
 
@@ -62,6 +62,13 @@ def _declare(L):
     L.oracle_median3x3.argtypes = [P, I, I, P]
     L.oracle_disparity_ex.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P, P, P]
     L.oracle_densify.argtypes = [P, P, I, I, P, P]
+    L.oracle_splitmix64.argtypes = [ct.c_uint64, ct.c_uint64]
+    L.oracle_splitmix64.restype = ct.c_uint64
+    L.oracle_pyr_down.argtypes = [P, I, I, P]
+    L.oracle_flow_cost.argtypes = [P, P, I, I, I, I, I, I]
+    L.oracle_pm_flow.argtypes = [P, P, I, I, I, I, I, ct.c_uint64, P]
+    L.oracle_fb_check.argtypes = [P, P, I, I, I, P]
+    L.oracle_flow.argtypes = [P, P, I, I, I, I, I, ct.c_uint64, I, P, P, P]
     L.oracle_features.argtypes = [P, I, P, P, I, I, I, I, P]
     L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
     L.oracle_lrnet.restype = ct.c_double
@@ -221,6 +228,58 @@ def densify(sf4, valid):
     fill = np.zeros((H, W), np.uint8)
     lib().oracle_densify(_p(s), _p(v), H, W, _p(out), _p(fill))
     return out, fill
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    return int(lib().oracle_splitmix64(seed, counter))
+
+
+def pyr_down(img):
+    a = np.ascontiguousarray(img, np.uint8)
+    H, W = a.shape
+    out = np.zeros(((H + 1) // 2, (W + 1) // 2), np.uint8)
+    lib().oracle_pyr_down(_p(a), H, W, _p(out))
+    return out
+
+
+def flow_cost(c0, c1, x, y, fu, fv):
+    a = np.ascontiguousarray(c0, np.uint64)
+    b = np.ascontiguousarray(c1, np.uint64)
+    H, W = a.shape
+    return int(lib().oracle_flow_cost(_p(a), _p(b), H, W, x, y, fu, fv))
+
+
+def pm_flow(A, B, levels=5, iters=4, R=128, seed=1801):
+    """Integer flow [H][W][2] int16 from A to B (the stand-in without the check)."""
+    a = np.ascontiguousarray(A, np.uint8)
+    b = np.ascontiguousarray(B, np.uint8)
+    H, W = a.shape
+    assert 1 <= levels <= 16
+    out = np.zeros((H, W, 2), np.int16)
+    lib().oracle_pm_flow(_p(a), _p(b), H, W, levels, iters, R, seed, _p(out))
+    return out
+
+
+def fb_check(F, B, tol=1):
+    f = np.ascontiguousarray(F, np.int16)
+    b = np.ascontiguousarray(B, np.int16)
+    H, W = f.shape[:2]
+    out = np.zeros((H, W, 2), np.float32)
+    lib().oracle_fb_check(_p(f), _p(b), H, W, tol, _p(out))
+    return out
+
+
+def flow(L0, L1, levels=5, iters=4, R=128, seed=1801, tol=1):
+    """Forward, backward integer flows and the checked float flow (NaN where dropped)."""
+    a = np.ascontiguousarray(L0, np.uint8)
+    b = np.ascontiguousarray(L1, np.uint8)
+    H, W = a.shape
+    assert 1 <= levels <= 16
+    F = np.zeros((H, W, 2), np.int16)
+    B = np.zeros((H, W, 2), np.int16)
+    out = np.zeros((H, W, 2), np.float32)
+    lib().oracle_flow(_p(a), _p(b), H, W, levels, iters, R, seed, tol, _p(F), _p(B), _p(out))
+    return F, B, out
 
 
 DIAG, MEDIAN, ADAPTIVE = 1, 2, 4
