@@ -360,6 +360,40 @@ int sf_densify(const float *sf4, const uint8_t *valid, int H, int W, float *out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Optical-flow stand-in for the flow input of the combination.  The paper
+ * takes its flow from Flow Fields+ (Sec. 3.2: coarse-level matches propagated
+ * to neighbours and refined by random search under a patch data term, lifted
+ * level by level, filtered by consistency with the inverse flow); this is a
+ * method of the same outline with choices of its own, all integer:
+ *   - pyramid of `levels` levels, each the 2x2 box mean (a+b+c+d+2)/4 of the
+ *     finer one (odd borders clamped);
+ *   - data term at each level: the 9x7 census of sf_census; the cost of
+ *     integer flow f at x is sum over o in {-2,0,2}^2 of the Hamming distance
+ *     of census0(x + o) and census1(x + f + o), coordinates clamped; targets
+ *     outside the image are no candidates;
+ *   - `iters` iterations per level, each updating all pixels from the previous
+ *     field: own f, the f of the neighbours at distance 1 then 4 (left, right,
+ *     up, down), then random search around the best so far with radii
+ *     R_l >> k (R_l = max(1, R >> l)), offsets from SplitMix64 output
+ *     (seed, counter (((l*64 + iter)*64 + k)*65536 + y)*65536 + x) as
+ *     ((h & 0xFFFF) mod (2r+1)) - r and (((h >> 16) & 0xFFFF) mod (2r+1)) - r;
+ *     the first candidate with the lowest cost wins;
+ *   - f = 0 on the coarsest level; f(x, y) = 2 f_coarser(x/2, y/2), target
+ *     clamped into the image, when moving one level finer;
+ *   - forward flow F (L0 -> L1, seed) and backward flow B (L1 -> L0, seed ^
+ *     0x5bd1e995); flow(x) = F(x) if |F(x) + B(x + F(x))| <= tol in both
+ *     components, else NaN (the combination then leaves S undefined there).
+ *   L0, L1 [H][pitch] uint8; F, B [H][W][2] int16 (outputs, 4-byte aligned);
+ *   flow [H][W][2] float (output, 8-byte aligned); workspace of at least
+ *   sf_flow_workspace_bytes(H, W, levels) bytes.
+ * Supported: H, W <= 16383; levels in [1, 16]; iters in [1, 63]; R in
+ * [1, 16383].  Errors: SF_EINVAL, SF_ENOMEM, SF_EHIP. */
+size_t sf_flow_workspace_bytes(int H, int W, int levels);
+int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, int W, int levels, int iters,
+            int R, uint64_t seed, int tol, int16_t *F, int16_t *B, float *flow, void *workspace,
+            size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Machine-balance probes (not part of the method): the measured ceilings the
  * kernels' roofline fractions are also quoted against.
  *

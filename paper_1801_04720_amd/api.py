@@ -224,6 +224,30 @@ def densify(sf4, valid, out=None, stream=None):
     return {"sf4": dense, "fill": fill}
 
 
+def flow(L0, L1, levels: int = 5, iters: int = 6, R: int = 128, seed: int = 1801, tol: int = 1,
+         out=None, stream=None):
+    """Optical-flow stand-in -> {"flow": [H][W][2] float (NaN where the
+    forward-backward check drops it), "F", "B": [H][W][2] int16}."""
+    H, W = L0.shape
+    dev = L0.device
+    o = out or {}
+    F = o.get("F")
+    if F is None:
+        F = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
+    B = o.get("B")
+    if B is None:
+        B = torch.empty((H, W, 2), dtype=torch.int16, device=dev)
+    fl = o.get("flow")
+    if fl is None:
+        fl = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
+    ws = o.get("workspace")
+    if ws is None:
+        ws = torch.empty(lib().sf_flow_workspace_bytes(H, W, levels), dtype=torch.uint8, device=dev)
+    check(lib().sf_flow(_ptr(L0), _ptr(L1), L0.stride(0), H, W, levels, iters, R, seed, tol, _ptr(F),
+                        _ptr(B), _ptr(fl), _ptr(ws), ws.numel(), _stream(stream)))
+    return {"flow": fl, "F": F, "B": B, "workspace": ws}
+
+
 FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN, FRAME_ADAPTIVE_P2 = 1, 2, 4, 8, 16
 
 
