@@ -441,6 +441,56 @@ def variants_leg(args, plain_pipe, inputs, fr, H, W, D, ms_plain, dev):
             "speedup_diag_vs_plain": res["diag"]["speedup_vs_plain"]}
 
 
+def flow_leg(args, plain_pipe, inputs, fr, H, W, D, dev):
+    """Optical-flow stand-in on the frame's two left images: GPU ms per flow field
+    (forward + backward + consistency check) for a few iteration counts, its
+    quality against the generator's flow (end-point error on the kept pixels,
+    Fl outliers, density), and the whole scene flow computed from the four
+    images alone (flow + plain frame): ms and Table-1 outliers Est / All."""
+    import torch
+
+    from paper_1801_04720_amd import _lib, api
+    from paper_1801_04720_amd.evaluate import sf_outliers
+
+    lib = _lib.lib()
+    L0, R0, L1, R1, _ = inputs
+    gt = torch.from_numpy(fr.gt_flow).to(dev)
+    res = {}
+    buf = api.flow(L0, L1, levels=5, iters=2, R=128)
+    for iters in (2, 4, 6, 8):
+        api.flow(L0, L1, levels=5, iters=iters, R=128, out=buf)
+        torch.cuda.synchronize()
+        _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
+        for _ in range(max(1, args.steps // 3)):
+            api.flow(L0, L1, levels=5, iters=iters, R=128, out=buf)
+        torch.cuda.synchronize()
+        lib.sf_prof_disable()
+        tot, n = kernel_ms(lib, "flow")
+        fl = buf["flow"]
+        kept = ~torch.isnan(fl[..., 0])
+        err = torch.linalg.norm(fl - gt, dim=-1)
+        gtn = torch.linalg.norm(gt, dim=-1)
+        res[f"levels5_iters{iters}_R128"] = {
+            "ms": tot / max(n, 1), "density": float(kept.float().mean().item()),
+            "epe_kept": float(err[kept].mean().item()),
+            "fl_outliers_kept_pct": float(100.0 * ((err > 3) & (err > 0.05 * gtn))[kept].float().mean().item())}
+    # Scene flow from images alone with 6 iterations per level.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 3)):
+        api.flow(L0, L1, levels=5, iters=6, R=128, out=buf)
+        out = plain_pipe.run(L0, R0, L1, R1, buf["flow"])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 3)
+    dense = api.densify(out["sf4"], out["valid"])
+    gts = (fr.gt_flow, fr.t0.gt_disp, fr.gt_disp1_at_t0)
+    res["scene_flow_from_images"] = {
+        "ms": ms, "fps": 1e3 / ms, "flow": "levels 5, iters 6, R 128",
+        "sf_outliers_est": sf_outliers(out["sf4"], out["valid"] & 1, *gts),
+        "sf_outliers_all": sf_outliers(dense["sf4"], dense["fill"] > 0, *gts)}
+    return {"flow_standin": res}
+
+
 def bench_peaks(args, dev):
     """Measured ceilings: HBM stream rates (2 GiB buffers, far above the 256 MB
     last-level cache), the same copy on a 64 MiB buffer that the last-level cache
@@ -493,6 +543,7 @@ def main():
                          "blocks; stages: one C-ABI call per stage")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
+    ap.add_argument("--no-flow", action="store_true", help="skip the optical-flow stand-in leg")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the SGM-variant legs (diagonal search, median, adaptive P2)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -638,6 +689,8 @@ def main():
         res.update(learned_leg(args, pipe, (L0, R0, L1, R1, flow), H, W, D, ms, dev))
     if not args.no_variants and args.pipeline != "stages":
         res.update(variants_leg(args, pipe, (L0, R0, L1, R1, flow), fr, H, W, D, ms, dev))
+    if not args.no_flow and args.pipeline != "stages":
+        res.update(flow_leg(args, pipe, (L0, R0, L1, R1, flow), fr, H, W, D, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)

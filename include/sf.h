@@ -375,7 +375,8 @@ int sf_densify(const float *sf4, const uint8_t *valid, int H, int W, float *out,
  *     field: own f, the f of the neighbours at distance 1 then 4 (left, right,
  *     up, down), then random search around the best so far with radii
  *     R_l >> k (R_l = max(1, R >> l)), offsets from SplitMix64 output
- *     (seed, counter (((l*64 + iter)*64 + k)*65536 + y)*65536 + x) as
+ *     (seed, counter (((l*64 + iter)*64 + k)*65536 + y/8)*65536 + x/8, one
+ *     offset per 8x8 tile) as
  *     ((h & 0xFFFF) mod (2r+1)) - r and (((h >> 16) & 0xFFFF) mod (2r+1)) - r;
  *     the first candidate with the lowest cost wins;
  *   - f = 0 on the coarsest level; f(x, y) = 2 f_coarser(x/2, y/2), target

@@ -29,9 +29,10 @@
  *     in this order on ties;
  *   - random offsets: h = SplitMix64 output for counter c (the generator's
  *     finaliser applied to seed + (c + 1) * 0x9e3779b97f4a7c15) with
- *     c = (((level * 64 + iter) * 64 + k) * 65536 + y) * 65536 + x; the
- *     offset is ((h & 0xFFFF) mod (2r+1)) - r horizontally and
- *     (((h >> 16) & 0xFFFF) mod (2r+1)) - r vertically;
+ *     c = (((level * 64 + iter) * 64 + k) * 65536 + y/8) * 65536 + x/8, so
+ *     the pixels of one 8x8 tile share the offset (each still searches around
+ *     its own best flow); the offset is ((h & 0xFFFF) mod (2r+1)) - r
+ *     horizontally and (((h >> 16) & 0xFFFF) mod (2r+1)) - r vertically;
  *   - consistency: forward flow F at x is kept iff the backward flow B (the
  *     same method from the second image to the first, with seed
  *     seed ^ 0x5bd1e995) at x' = x + F(x)
@@ -124,9 +125,9 @@ static void pm_iteration(const uint64_t *c0, const uint64_t *c1, int H, int W, i
             for (int k = 0; (Rl >> k) >= 1; ++k) {
                 const int r = Rl >> k;
                 const uint64_t ctr =
-                    ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)y) *
+                    ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)(y / 8)) *
                         65536 +
-                    (uint64_t)x;
+                    (uint64_t)(x / 8);
                 const uint64_t h = oracle_splitmix64(seed, ctr);
                 const int ou = (int)((h & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;
                 const int ov = (int)(((h >> 16) & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;

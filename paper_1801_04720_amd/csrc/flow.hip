@@ -12,8 +12,9 @@
 //   * each iteration updates all pixels from the previous field: own f, the f
 //     of the neighbours at distance 1 then 4 (left, right, up, down), then
 //     random search around the best so far with radii R_l >> k, offsets drawn
-//     from SplitMix64 (counter = (((level*64 + iter)*64 + k)*65536 + y)*65536
-//     + x); the first candidate with the lowest cost wins;
+//     from SplitMix64 (counter = (((level*64 + iter)*64 + k)*65536 + y/8)*65536
+//     + x/8: one offset per 8x8 tile, so a wave's candidate loads stay mostly
+//     contiguous); the first candidate with the lowest cost wins;
 //   * coarse to fine: f = 0 on the coarsest level, f = 2 f(x/2, y/2) with the
 //     target clamped into the image when moving one level finer;
 //   * forward-backward check: F(x) is kept iff |F(x) + B(x + F(x))| <= tol in
@@ -111,8 +112,9 @@ __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__r
     for (int k = 0; (Rl >> k) >= 1; ++k) {
         const int r = Rl >> k;
         const uint64_t ctr =
-            ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)y) * 65536 +
-            (uint64_t)x;
+            ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)(y >> 3)) *
+                65536 +
+            (uint64_t)(x >> 3);
         const uint64_t h = splitmix64(seed, ctr);
         const uint32_t m = (uint32_t)(2 * r + 1);
         const int ou = (int)((uint32_t)(h & 0xFFFFu) % m) - r;
