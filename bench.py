@@ -491,6 +491,51 @@ def flow_leg(args, plain_pipe, inputs, fr, H, W, D, dev):
     return {"flow_standin": res}
 
 
+def sequence_leg(args, dev, T=8):
+    """Scene flow over T = 8 time steps of one 1242x375 D=128 rig (flow within
+    60 px): the T disparity maps in one batch plan (a HIP graph), the T-1
+    combinations and the T-2 temporal checks.  Reports ms per time step and
+    the Table-1 outlier rates of the scene-flow maps before and after the
+    temporal validation, with their densities."""
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import synth
+    from paper_1801_04720_amd.evaluate import sf_outliers
+    from paper_1801_04720_amd.pipeline import SequenceFrames
+
+    s = synth.sequence_planar(synth.rng_for(6, 0), T, 375, 1242, 128, 60.0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    lefts, rights = [t(p.left) for p in s.pairs], [t(p.right) for p in s.pairs]
+    flows = [t(f) for f in s.flows]
+    seq = SequenceFrames(lefts, rights, 128, device=dev)
+    st = torch.cuda.Stream()  # graph capture needs a stream of its own
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        seq.batch.capture(st)
+        for _ in range(2):
+            seq.run(flows)
+        torch.cuda.synchronize()
+        reps = max(1, args.steps // 3)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, S, tv = seq.run(flows)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+    before, after = [], []
+    for k in range(T - 2):
+        gts = (s.gt_flows[k], s.pairs[k].gt_disp, s.gt_d1[k])
+        before.append(sf_outliers(S[k]["sf4"], S[k]["valid"] & 1, *gts))
+        after.append(sf_outliers(S[k]["sf4"], tv[k], *gts))
+    mean = lambda rs, key: float(np.mean([r[key] for r in rs]))  # noqa: E731
+    return {"sequence": {
+        "workload": f"{T} time steps 1242x375 D=128, flow within 60 px",
+        "ms_per_sequence": ms, "ms_per_time_step": ms / T,
+        "sf_outliers_before": {k: mean(before, k) for k in ("density", "D1", "D2", "Fl", "SF")},
+        "sf_outliers_temporally_validated": {k: mean(after, k) for k in ("density", "D1", "D2", "Fl", "SF")},
+        "tau_f_px": seq.tau_f, "tau_d_px": seq.tau_d}}
+
+
 def bench_peaks(args, dev):
     """Measured ceilings: HBM stream rates (2 GiB buffers, far above the 256 MB
     last-level cache), the same copy on a 64 MiB buffer that the last-level cache
@@ -544,6 +589,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-frame leg")
     ap.add_argument("--no-flow", action="store_true", help="skip the optical-flow stand-in leg")
+    ap.add_argument("--no-sequence", action="store_true",
+                    help="skip the multi-time-step leg with temporal validation")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the SGM-variant legs (diagonal search, median, adaptive P2)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -691,6 +738,8 @@ def main():
         res.update(variants_leg(args, pipe, (L0, R0, L1, R1, flow), fr, H, W, D, ms, dev))
     if not args.no_flow and args.pipeline != "stages":
         res.update(flow_leg(args, pipe, (L0, R0, L1, R1, flow), fr, H, W, D, dev))
+    if not args.no_sequence and args.pipeline != "stages":
+        res.update(sequence_leg(args, dev))
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(fr, D)
     print(json.dumps(res), flush=True)

@@ -360,6 +360,21 @@ int sf_densify(const float *sf4, const uint8_t *valid, int H, int W, float *out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Temporal validation over more than two frame pairs (the paper's future work:
+ * more frame pairs with an intermediate validation of the correspondences; the
+ * rule is this library's).  sf4_a / valid_a is the scene flow between t_k and
+ * t_k+1 (as sf_combine writes it), sf4_b / valid_b the one between t_k+1 and
+ * t_k+2.  out(x) = 1 iff S_a(x) = (u, v, d0, d1) is defined, the chained pixel
+ * q = (floor(x + u + 0.5), floor(y + v + 0.5)) lies in the image, S_b(q) =
+ * (u', v', d0', d1') is defined, |u - u'| <= tau_f, |v - v'| <= tau_f and
+ * |(d1 - d0) - (d1' - d0')| <= tau_d (FP32, in this order); else 0.
+ *   sf4_a, sf4_b [H][W][4] float (16-byte aligned); valid_a, valid_b, out
+ *   [H][W] uint8.  Errors: SF_EINVAL. */
+int sf_temporal_check(const float *sf4_a, const uint8_t *valid_a, const float *sf4_b,
+                      const uint8_t *valid_b, int H, int W, float tau_f, float tau_d, uint8_t *out,
+                      void *stream);
+
+/* ---------------------------------------------------------------------------
  * Optical-flow stand-in for the flow input of the combination.  The paper
  * takes its flow from Flow Fields+ (Sec. 3.2: coarse-level matches propagated
  * to neighbours and refined by random search under a patch data term, lifted

@@ -62,6 +62,7 @@ def _declare(L):
     L.oracle_median3x3.argtypes = [P, I, I, P]
     L.oracle_disparity_ex.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P, P, P]
     L.oracle_densify.argtypes = [P, P, I, I, P, P]
+    L.oracle_temporal_check.argtypes = [P, P, P, P, I, I, F, F, P]
     L.oracle_splitmix64.argtypes = [ct.c_uint64, ct.c_uint64]
     L.oracle_splitmix64.restype = ct.c_uint64
     L.oracle_pyr_down.argtypes = [P, I, I, P]
@@ -228,6 +229,18 @@ def densify(sf4, valid):
     fill = np.zeros((H, W), np.uint8)
     lib().oracle_densify(_p(s), _p(v), H, W, _p(out), _p(fill))
     return out, fill
+
+
+def temporal_check(sf4a, va, sf4b, vb, tau_f=2.0, tau_d=1.0):
+    """1 where S_k is kept by the check against S_{k+1} along its own flow."""
+    a = np.ascontiguousarray(sf4a, np.float32)
+    b = np.ascontiguousarray(sf4b, np.float32)
+    pa = np.ascontiguousarray(va, np.uint8)
+    pb = np.ascontiguousarray(vb, np.uint8)
+    H, W = pa.shape
+    out = np.zeros((H, W), np.uint8)
+    lib().oracle_temporal_check(_p(a), _p(pa), _p(b), _p(pb), H, W, tau_f, tau_d, _p(out))
+    return out
 
 
 def splitmix64(seed: int, counter: int) -> int:

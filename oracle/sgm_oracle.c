@@ -519,3 +519,42 @@ void oracle_densify(const float *sf4, const uint8_t *valid, int H, int W, float 
     }
     free(rowok);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Temporal validation over more than two frame pairs (the paper's future work:
+ * extend the method to more frame pairs with an intermediate validation of the
+ * correspondences; the rule is defined here).  With scene flow S_k between t_k
+ * and t_{k+1} and S_{k+1} between t_{k+1} and t_{k+2}, pixel x is kept in S_k
+ * iff
+ *   - S_k(x) = (u, v, d0, d1) is defined;
+ *   - q = (floor(x + u + 0.5), floor(y + v + 0.5)), the chained pixel at
+ *     t_{k+1}, lies in the image and S_{k+1}(q) = (u', v', d0', d1') is
+ *     defined;
+ *   - |u - u'| <= tau_f, |v - v'| <= tau_f and |(d1 - d0) - (d1' - d0')| <=
+ *     tau_d (motion nearly constant over the three time steps), all in FP32
+ *     in this order.
+ * sf4a, sf4b [H][W][4]; valid_a, valid_b [H][W] (bit 0); out [H][W] uint8. */
+void oracle_temporal_check(const float *sf4a, const uint8_t *va, const float *sf4b,
+                           const uint8_t *vb, int H, int W, float tau_f, float tau_d, uint8_t *out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const size_t i = (size_t)y * W + x;
+            uint8_t ok = 0;
+            if (va[i] & 1) {
+                const float *a = sf4a + 4 * i;
+                const float xq = floorf(((float)x + a[0]) + 0.5f);
+                const float yq = floorf(((float)y + a[1]) + 0.5f);
+                if (xq >= 0.0f && xq <= (float)(W - 1) && yq >= 0.0f && yq <= (float)(H - 1)) {
+                    const size_t j = (size_t)yq * W + (size_t)xq;
+                    if (vb[j] & 1) {
+                        const float *b = sf4b + 4 * j;
+                        const float ca = a[3] - a[2], cb = b[3] - b[2];
+                        ok = fabsf(a[0] - b[0]) <= tau_f && fabsf(a[1] - b[1]) <= tau_f &&
+                             fabsf(ca - cb) <= tau_d;
+                    }
+                }
+            }
+            out[i] = ok;
+        }
+}

@@ -224,6 +224,17 @@ def densify(sf4, valid, out=None, stream=None):
     return {"sf4": dense, "fill": fill}
 
 
+def temporal_check(sf4_a, valid_a, sf4_b, valid_b, tau_f: float = 2.0, tau_d: float = 1.0,
+                   out=None, stream=None):
+    """uint8 [H][W]: 1 where S_a is kept by the check against S_b along its flow."""
+    H, W = valid_a.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.uint8, device=valid_a.device)
+    check(lib().sf_temporal_check(_ptr(sf4_a), _ptr(valid_a), _ptr(sf4_b), _ptr(valid_b), H, W,
+                                  float(tau_f), float(tau_d), _ptr(out), _stream(stream)))
+    return out
+
+
 def flow(L0, L1, levels: int = 5, iters: int = 6, R: int = 128, seed: int = 1801, tol: int = 1,
          out=None, stream=None):
     """Optical-flow stand-in -> {"flow": [H][W][2] float (NaN where the

@@ -76,6 +76,37 @@ __global__ __launch_bounds__(256) void combine_kernel(
     valid[i] = vb;
 }
 
+// Temporal validation over three time steps: S_a (t_k -> t_k+1) is kept at x
+// iff the chained pixel q = floor(x + (u, v) + 0.5) at t_k+1 lies in the image,
+// S_b (t_k+1 -> t_k+2) is defined there, and the flows and disparity changes
+// agree within tau_f and tau_d (FP32, in this order).  One thread per pixel.
+__global__ __launch_bounds__(256) void temporal_check_kernel(const float4 *__restrict__ a,
+                                                             const uint8_t *__restrict__ va,
+                                                             const float4 *__restrict__ b,
+                                                             const uint8_t *__restrict__ vb, int H,
+                                                             int W, float tau_f, float tau_d,
+                                                             uint8_t *__restrict__ out)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= H * W) return;
+    const int y = i / W, x = i - y * W;
+    uint8_t ok = 0;
+    if (va[i] & 1) {
+        const float4 s = a[i];
+        const float xq = floorf(__fadd_rn((float)x, s.x) + 0.5f);
+        const float yq = floorf(__fadd_rn((float)y, s.y) + 0.5f);
+        if (xq >= 0.0f && xq <= (float)(W - 1) && yq >= 0.0f && yq <= (float)(H - 1)) {
+            const size_t j = (size_t)yq * W + (size_t)xq;
+            if (vb[j] & 1) {
+                const float4 t = b[j];
+                const float ca = s.w - s.z, cb = t.w - t.z;
+                ok = fabsf(s.x - t.x) <= tau_f && fabsf(s.y - t.y) <= tau_f && fabsf(ca - cb) <= tau_d;
+            }
+        }
+    }
+    out[i] = ok;
+}
+
 int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
                    const uint8_t *valid1, const float *flow, int H, int W, const sf_camera *cam,
                    float *sf4, uint8_t *valid, float *xyz0, float *motion, hipStream_t st)
@@ -107,4 +138,22 @@ extern "C" int sf_combine(const float *disp0, const uint8_t *valid0, const float
     if (cam) SF_REQUIRE(cam->f != 0.0f, SF_EINVAL, "sf_combine: focal length is zero");
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion,
                           as_stream(stream));
+}
+
+extern "C" int sf_temporal_check(const float *sf4_a, const uint8_t *valid_a, const float *sf4_b,
+                                 const uint8_t *valid_b, int H, int W, float tau_f, float tau_d,
+                                 uint8_t *out, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(sf4_a && valid_a && sf4_b && valid_b && out, SF_EINVAL, "sf_temporal_check: NULL pointer");
+    SF_REQUIRE(H > 0 && W > 0 && (long long)H * W <= (1LL << 30), SF_EINVAL,
+               "sf_temporal_check: bad image size");
+    SF_REQUIRE(tau_f >= 0.0f && tau_d >= 0.0f, SF_EINVAL, "sf_temporal_check: negative tolerance");
+    SF_REQUIRE((reinterpret_cast<uintptr_t>(sf4_a) | reinterpret_cast<uintptr_t>(sf4_b)) % 16 == 0,
+               SF_EINVAL, "sf_temporal_check: sf4 buffers must be 16-byte aligned");
+    const int n = H * W;
+    hipLaunchKernelGGL(temporal_check_kernel, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream),
+                       reinterpret_cast<const float4 *>(sf4_a), valid_a,
+                       reinterpret_cast<const float4 *>(sf4_b), valid_b, H, W, tau_f, tau_d, out);
+    return launch_status("temporal_check_kernel");
 }

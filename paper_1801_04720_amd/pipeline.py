@@ -112,3 +112,46 @@ class FusedFrame:
             return api.frame_run_learned(self.plan, L0, R0, L1, R1, flow, self.cam, self.params,
                                          self.out, self.ws)
         return api.frame_run(self.plan, L0, R0, L1, R1, flow, self.cam, self.out, self.ws)
+
+
+class SequenceFrames:
+    """Scene flow over T time steps of one stereo rig (the paper's future work:
+    more than two frame pairs with an intermediate validation): every time
+    step's disparity map is computed once (the T pairs in one batch plan), the
+    combination runs for each consecutive pair, and each scene-flow map but the
+    last is checked against the next one along its own flow.
+
+    lefts, rights: T uint8 [H][W] tensors on the GPU (bound to the plan)."""
+
+    def __init__(self, lefts, rights, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1,
+                 cam=(721.5, 0.54, None, None), tau_f: float = 2.0, tau_d: float = 1.0,
+                 tuning=None, device="cuda:0"):
+        from . import batch as _batch
+
+        self.T = len(lefts)
+        H, W = lefts[0].shape
+        self.H, self.W, self.D = H, W, D
+        f, B, cx, cy = cam
+        self.cam = (f, B, (W - 1) / 2.0 if cx is None else cx, (H - 1) / 2.0 if cy is None else cy)
+        self.tau_f, self.tau_d = tau_f, tau_d
+        pairs = [{"left": L, "right": R, "D": D} for L, R in zip(lefts, rights)]
+        self.batch = _batch.Batch(pairs, P1, P2, lr_tol, tunings=[tuning] if tuning is not None else None,
+                                  device=device)
+        dev = torch.device(device)
+        e = lambda *s, dt: torch.empty(s, dtype=dt, device=dev)  # noqa: E731
+        self.S = [{"sf4": e(H, W, 4, dt=torch.float32), "valid": e(H, W, dt=torch.uint8),
+                   "xyz0": e(H, W, 3, dt=torch.float32), "motion": e(H, W, 3, dt=torch.float32)}
+                  for _ in range(self.T - 1)]
+        self.temporal = [e(H, W, dt=torch.uint8) for _ in range(max(0, self.T - 2))]
+
+    def run(self, flows):
+        """flows: T-1 float [H][W][2] tensors (t_k -> t_k+1).  Returns (maps,
+        scene flows, temporal masks)."""
+        maps = self.batch.launch() if self.batch.captured else self.batch.run()
+        for k in range(self.T - 1):
+            api.combine(maps[k]["disp"], maps[k]["valid"], maps[k + 1]["disp"], maps[k + 1]["valid"],
+                        flows[k], self.cam, out=self.S[k])
+        for k in range(self.T - 2):
+            api.temporal_check(self.S[k]["sf4"], self.S[k]["valid"], self.S[k + 1]["sf4"],
+                               self.S[k + 1]["valid"], self.tau_f, self.tau_d, out=self.temporal[k])
+        return maps, self.S, self.temporal

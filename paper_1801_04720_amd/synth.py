@@ -290,6 +290,62 @@ def frame_planar(rng: np.random.Generator, H: int, W: int, D: int, flow_max: flo
     return Frame(t0, t1, flow, gt_flow, d1.astype(np.float32), D)
 
 
+@dataclass
+class Sequence:
+    pairs: list          # StereoPair per time step t_0 .. t_{T-1}
+    flows: list          # float32 [H][W][2]: the given (noisy) flow t_k -> t_{k+1}
+    gt_flows: list       # float32 [H][W][2]
+    gt_d1: list          # float32 [H][W]: disparity at t_{k+1} of each t_k pixel
+    D: int
+
+
+def sequence_planar(rng: np.random.Generator, T: int, H: int, W: int, D: int, flow_max: float,
+                    K: int = 6) -> Sequence:
+    """T stereo pairs of one scene: the t_0 pair is piecewise planar
+    (``pair_planar``); every region keeps one affine 2-D velocity (small
+    gradients, so motion is nearly constant from step to step) and one
+    disparity change per step within +-2 px.  Each step forward-splats the left
+    image, its disparities and region labels along the ground-truth flow
+    (nearer surface wins; holes get noise and keep their previous disparity
+    and label) and renders the right image along the new disparities.  The
+    flow handed to the method is ground truth plus N(0, 0.5^2) per component."""
+    t0, lab = _pair_planar_labels(rng, H, W, D, K)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    nlab = K + 1
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    u0 = rng.uniform(-0.6, 0.6, nlab) * flow_max
+    v0 = rng.uniform(-0.2, 0.2, nlab) * flow_max
+    ux = rng.uniform(-0.01, 0.01, nlab)
+    uy = rng.uniform(-0.01, 0.01, nlab)
+    vx = rng.uniform(-0.01, 0.01, nlab)
+    vy = rng.uniform(-0.01, 0.01, nlab)
+    e0 = rng.uniform(-2.0, 2.0, nlab)
+    u0[0], v0[0] = 0.0, 0.0
+    ux[0], uy[0], vx[0], vy[0] = 0.01, 0.0, 0.0, 0.01
+    pairs, flows, gt_flows, gt_d1 = [t0], [], [], []
+    L, d, lb = t0.left, t0.gt_disp.astype(np.float64), lab
+    for _ in range(T - 1):
+        gu = np.clip(u0[lb] + ux[lb] * (xs - cx) + uy[lb] * (ys - cy), -flow_max, flow_max)
+        gv = np.clip(v0[lb] + vx[lb] * (xs - cx) + vy[lb] * (ys - cy), -flow_max, flow_max)
+        d1 = np.clip(d + e0[lb], 0, D - 1)
+        gt = np.stack([gu, gv], -1).astype(np.float32)
+        gt_flows.append(gt)
+        flows.append((gt + rng.normal(0.0, 0.5, size=(H, W, 2))).astype(np.float32))
+        gt_d1.append(d1.astype(np.float32))
+        tx, ty = (xs + gu).reshape(-1), (ys + gv).reshape(-1)
+        noise_img = rng.integers(0, 256, size=(H, W), dtype=np.int32).astype(np.uint8)
+        L1, hit = _splat(L.reshape(-1), d1.reshape(-1), tx, ty, H, W, noise_img)
+        D1grid, _ = _splat(d1.reshape(-1), d1.reshape(-1), tx, ty, H, W, d)
+        lab1, _ = _splat(lb.reshape(-1), d1.reshape(-1), tx, ty, H, W, lb)
+        noise_r = rng.integers(0, 256, size=(H, W), dtype=np.int32).astype(np.uint8)
+        R1, _ = _splat(L1.reshape(-1), D1grid.reshape(-1), (xs - D1grid).reshape(-1),
+                       ys.reshape(-1), H, W, noise_r)
+        pairs.append(StereoPair(L1.astype(np.uint8), R1.astype(np.uint8), D1grid.astype(np.float32),
+                                ~hit, _disc_real(D1grid), D))
+        L, d, lb = L1.astype(np.uint8), D1grid, lab1.astype(lab.dtype)
+    return Sequence(pairs, flows, gt_flows, gt_d1, D)
+
+
 def _disc_real(d: np.ndarray) -> np.ndarray:
     """Pixels next to a jump of more than half a pixel in a disparity map."""
     disc = np.zeros(d.shape, bool)
