@@ -457,12 +457,12 @@ def flow_leg(args, plain_pipe, inputs, fr, H, W, D, dev):
     gt = torch.from_numpy(fr.gt_flow).to(dev)
     res = {}
     buf = api.flow(L0, L1, levels=5, iters=2, R=128)
-    for iters in (2, 4, 6, 8):
-        api.flow(L0, L1, levels=5, iters=iters, R=128, out=buf)
+    for iters, fine in ((2, 0), (4, 0), (6, 0), (8, 0), (4, 8), (6, 8)):
+        api.flow(L0, L1, levels=5, iters=iters, R=128, fine_radius=fine, out=buf)
         torch.cuda.synchronize()
         _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
         for _ in range(max(1, args.steps // 3)):
-            api.flow(L0, L1, levels=5, iters=iters, R=128, out=buf)
+            api.flow(L0, L1, levels=5, iters=iters, R=128, fine_radius=fine, out=buf)
         torch.cuda.synchronize()
         lib.sf_prof_disable()
         tot, n = kernel_ms(lib, "flow")
@@ -470,22 +470,22 @@ def flow_leg(args, plain_pipe, inputs, fr, H, W, D, dev):
         kept = ~torch.isnan(fl[..., 0])
         err = torch.linalg.norm(fl - gt, dim=-1)
         gtn = torch.linalg.norm(gt, dim=-1)
-        res[f"levels5_iters{iters}_R128"] = {
+        res[f"levels5_iters{iters}_R128" + (f"_fine{fine}" if fine else "")] = {
             "ms": tot / max(n, 1), "density": float(kept.float().mean().item()),
             "epe_kept": float(err[kept].mean().item()),
             "fl_outliers_kept_pct": float(100.0 * ((err > 3) & (err > 0.05 * gtn))[kept].float().mean().item())}
-    # Scene flow from images alone with 6 iterations per level.
+    # Scene flow from images alone with 4 iterations per level, fine-level radius 8.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(max(1, args.steps // 3)):
-        api.flow(L0, L1, levels=5, iters=6, R=128, out=buf)
+        api.flow(L0, L1, levels=5, iters=4, R=128, fine_radius=8, out=buf)
         out = plain_pipe.run(L0, R0, L1, R1, buf["flow"])
     torch.cuda.synchronize()
     ms = 1e3 * (time.perf_counter() - t0) / max(1, args.steps // 3)
     dense = api.densify(out["sf4"], out["valid"])
     gts = (fr.gt_flow, fr.t0.gt_disp, fr.gt_disp1_at_t0)
     res["scene_flow_from_images"] = {
-        "ms": ms, "fps": 1e3 / ms, "flow": "levels 5, iters 6, R 128",
+        "ms": ms, "fps": 1e3 / ms, "flow": "levels 5, iters 4, R 128, fine radius 8",
         "sf_outliers_est": sf_outliers(out["sf4"], out["valid"] & 1, *gts),
         "sf_outliers_all": sf_outliers(dense["sf4"], dense["fill"] > 0, *gts)}
     return {"flow_standin": res}

@@ -389,7 +389,8 @@ int sf_temporal_check(const float *sf4_a, const uint8_t *valid_a, const float *s
  *   - `iters` iterations per level, each updating all pixels from the previous
  *     field: own f, the f of the neighbours at distance 1 then 4 (left, right,
  *     up, down), then random search around the best so far with radii
- *     R_l >> k (R_l = max(1, R >> l)), offsets from SplitMix64 output
+ *     R_l >> k (R_l = max(1, R >> l), capped at fine_radius on every level
+ *     but the coarsest when fine_radius > 0), offsets from SplitMix64 output
  *     (seed, counter (((l*64 + iter)*64 + k)*65536 + y/8)*65536 + x/8, one
  *     offset per 8x8 tile) as
  *     ((h & 0xFFFF) mod (2r+1)) - r and (((h >> 16) & 0xFFFF) mod (2r+1)) - r;
@@ -403,11 +404,11 @@ int sf_temporal_check(const float *sf4_a, const uint8_t *valid_a, const float *s
  *   flow [H][W][2] float (output, 8-byte aligned); workspace of at least
  *   sf_flow_workspace_bytes(H, W, levels) bytes.
  * Supported: H, W <= 16383; levels in [1, 16]; iters in [1, 63]; R in
- * [1, 16383].  Errors: SF_EINVAL, SF_ENOMEM, SF_EHIP. */
+ * [1, 16383]; fine_radius >= 0.  Errors: SF_EINVAL, SF_ENOMEM, SF_EHIP. */
 size_t sf_flow_workspace_bytes(int H, int W, int levels);
 int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, int W, int levels, int iters,
-            int R, uint64_t seed, int tol, int16_t *F, int16_t *B, float *flow, void *workspace,
-            size_t ws_bytes, void *stream);
+            int R, int fine_radius, uint64_t seed, int tol, int16_t *F, int16_t *B, float *flow,
+            void *workspace, size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Machine-balance probes (not part of the method): the measured ceilings the

@@ -63,13 +63,15 @@ def _declare(L):
     L.oracle_disparity_ex.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P, P, P]
     L.oracle_densify.argtypes = [P, P, I, I, P, P]
     L.oracle_temporal_check.argtypes = [P, P, P, P, I, I, F, F, P]
+    L.oracle_aggregate_at.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint, I, I, P]
+    L.oracle_disparity_at.argtypes = [P, P, I, I, I, I, I, I, I, P, P, I, P, P, P]
     L.oracle_splitmix64.argtypes = [ct.c_uint64, ct.c_uint64]
     L.oracle_splitmix64.restype = ct.c_uint64
     L.oracle_pyr_down.argtypes = [P, I, I, P]
     L.oracle_flow_cost.argtypes = [P, P, I, I, I, I, I, I]
-    L.oracle_pm_flow.argtypes = [P, P, I, I, I, I, I, ct.c_uint64, P]
+    L.oracle_pm_flow.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint64, P]
     L.oracle_fb_check.argtypes = [P, P, I, I, I, P]
-    L.oracle_flow.argtypes = [P, P, I, I, I, I, I, ct.c_uint64, I, P, P, P]
+    L.oracle_flow.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint64, I, P, P, P]
     L.oracle_features.argtypes = [P, I, P, P, I, I, I, I, P]
     L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
     L.oracle_lrnet.restype = ct.c_double
@@ -231,6 +233,33 @@ def densify(sf4, valid):
     return out, fill
 
 
+def aggregate_at(cen_base, cen_match, D, base_is_right, P1, P2, x, y, path_mask=0xFF):
+    """S(x, y, .) [D] uint16 from the path recurrences along the lines into (x, y)."""
+    cb = np.ascontiguousarray(cen_base, np.uint64)
+    cm = np.ascontiguousarray(cen_match, np.uint64)
+    H, W = cb.shape
+    out = np.zeros(D, np.uint16)
+    lib().oracle_aggregate_at(_p(cb), _p(cm), H, W, D, int(base_is_right), P1, P2, path_mask, x, y,
+                              _p(out))
+    return out
+
+
+def disparity_at(left, right, D, xs, ys, P1=10, P2=120, tol=1):
+    """Plain disparity map (with LR check) at sampled pixels: (wta, disp, valid) per sample."""
+    L = np.ascontiguousarray(left, np.uint8)
+    R = np.ascontiguousarray(right, np.uint8)
+    H, W = L.shape
+    xs = np.ascontiguousarray(xs, np.int32)
+    ys = np.ascontiguousarray(ys, np.int32)
+    n = len(xs)
+    w = np.zeros(n, np.int16)
+    disp = np.zeros(n, np.float32)
+    valid = np.zeros(n, np.uint8)
+    lib().oracle_disparity_at(_p(L), _p(R), H, W, W, D, P1, P2, tol, _p(xs), _p(ys), n, _p(w),
+                              _p(disp), _p(valid))
+    return w, disp, valid
+
+
 def temporal_check(sf4a, va, sf4b, vb, tau_f=2.0, tau_d=1.0):
     """1 where S_k is kept by the check against S_{k+1} along its own flow."""
     a = np.ascontiguousarray(sf4a, np.float32)
@@ -262,14 +291,14 @@ def flow_cost(c0, c1, x, y, fu, fv):
     return int(lib().oracle_flow_cost(_p(a), _p(b), H, W, x, y, fu, fv))
 
 
-def pm_flow(A, B, levels=5, iters=4, R=128, seed=1801):
+def pm_flow(A, B, levels=5, iters=4, R=128, seed=1801, fine_radius=0):
     """Integer flow [H][W][2] int16 from A to B (the stand-in without the check)."""
     a = np.ascontiguousarray(A, np.uint8)
     b = np.ascontiguousarray(B, np.uint8)
     H, W = a.shape
     assert 1 <= levels <= 16
     out = np.zeros((H, W, 2), np.int16)
-    lib().oracle_pm_flow(_p(a), _p(b), H, W, levels, iters, R, seed, _p(out))
+    lib().oracle_pm_flow(_p(a), _p(b), H, W, levels, iters, R, fine_radius, seed, _p(out))
     return out
 
 
@@ -282,7 +311,7 @@ def fb_check(F, B, tol=1):
     return out
 
 
-def flow(L0, L1, levels=5, iters=4, R=128, seed=1801, tol=1):
+def flow(L0, L1, levels=5, iters=4, R=128, seed=1801, tol=1, fine_radius=0):
     """Forward, backward integer flows and the checked float flow (NaN where dropped)."""
     a = np.ascontiguousarray(L0, np.uint8)
     b = np.ascontiguousarray(L1, np.uint8)
@@ -291,7 +320,8 @@ def flow(L0, L1, levels=5, iters=4, R=128, seed=1801, tol=1):
     F = np.zeros((H, W, 2), np.int16)
     B = np.zeros((H, W, 2), np.int16)
     out = np.zeros((H, W, 2), np.float32)
-    lib().oracle_flow(_p(a), _p(b), H, W, levels, iters, R, seed, tol, _p(F), _p(B), _p(out))
+    lib().oracle_flow(_p(a), _p(b), H, W, levels, iters, R, fine_radius, seed, tol, _p(F), _p(B),
+                      _p(out))
     return F, B, out
 
 

@@ -25,7 +25,8 @@
  *     the f of its neighbours at distance 1 then 4 (left, right, up, down);
  *     then random search around the best candidate so far with radius
  *     r_k = R_l >> k for k = 0, 1, ... while r_k >= 1, where R_l = max(1,
- *     R >> l) for a full-resolution range R.  The lowest cost wins; the first
+ *     R >> l) for a full-resolution range R, capped at fine_radius on every
+ *     level but the coarsest when fine_radius > 0.  The lowest cost wins; the first
  *     in this order on ties;
  *   - random offsets: h = SplitMix64 output for counter c (the generator's
  *     finaliser applied to seed + (c + 1) * 0x9e3779b97f4a7c15) with
@@ -98,9 +99,8 @@ int oracle_flow_cost(const uint64_t *c0, const uint64_t *c1, int H, int W, int x
 
 /* One iteration on one level: flow_in / flow_out [H][W][2] int16. */
 static void pm_iteration(const uint64_t *c0, const uint64_t *c1, int H, int W, int level, int iter,
-                         int R, uint64_t seed, const int16_t *fin, int16_t *fout)
+                         int Rl, uint64_t seed, const int16_t *fin, int16_t *fout)
 {
-    const int Rl = (R >> level) > 1 ? (R >> level) : 1;
     const int du[4] = {-1, +1, 0, 0}, dv[4] = {0, 0, -1, +1};
     const int dist[2] = {1, 4};
     for (int y = 0; y < H; ++y)
@@ -148,7 +148,7 @@ static void pm_iteration(const uint64_t *c0, const uint64_t *c1, int H, int W, i
  * iters >= 1 per level, R >= 1 the full-resolution search range.  flow
  * [H][W][2] int16 (output). */
 void oracle_pm_flow(const uint8_t *A, const uint8_t *B, int H, int W, int levels, int iters, int R,
-                    uint64_t seed, int16_t *flow)
+                    int fine_radius, uint64_t seed, int16_t *flow)
 {
     uint8_t *pa[16], *pb[16];
     int hs[16], ws[16];
@@ -185,8 +185,10 @@ void oracle_pm_flow(const uint8_t *A, const uint8_t *B, int H, int W, int levels
             free(cur);
         }
         int16_t *g = (int16_t *)malloc((size_t)h * w * 2 * sizeof(int16_t));
+        int Rl = (R >> l) > 1 ? (R >> l) : 1;
+        if (l < levels - 1 && fine_radius > 0 && Rl > fine_radius) Rl = fine_radius;
         for (int it = 0; it < iters; ++it) {
-            pm_iteration(c0, c1, h, w, l, it, R, seed, f, g);
+            pm_iteration(c0, c1, h, w, l, it, Rl, seed, f, g);
             int16_t *t = f;
             f = g;
             g = t;
@@ -226,9 +228,9 @@ void oracle_fb_check(const int16_t *F, const int16_t *B, int H, int W, int tol, 
 
 /* The whole stand-in: forward and backward integer flows, then the check. */
 void oracle_flow(const uint8_t *L0, const uint8_t *L1, int H, int W, int levels, int iters, int R,
-                 uint64_t seed, int tol, int16_t *F, int16_t *B, float *out)
+                 int fine_radius, uint64_t seed, int tol, int16_t *F, int16_t *B, float *out)
 {
-    oracle_pm_flow(L0, L1, H, W, levels, iters, R, seed, F);
-    oracle_pm_flow(L1, L0, H, W, levels, iters, R, seed ^ 0x5bd1e995ULL, B);
+    oracle_pm_flow(L0, L1, H, W, levels, iters, R, fine_radius, seed, F);
+    oracle_pm_flow(L1, L0, H, W, levels, iters, R, fine_radius, seed ^ 0x5bd1e995ULL, B);
     oracle_fb_check(F, B, H, W, tol, out);
 }

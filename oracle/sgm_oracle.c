@@ -558,3 +558,95 @@ void oracle_temporal_check(const float *sf4a, const uint8_t *va, const float *sf
             out[i] = ok;
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Aggregated costs of one pixel, for checking large images at sampled pixels:
+ * each direction's recurrence is run only along the line of pixels p - k r
+ * (k = K .. 0, p - K r the first pixel inside the image), which is all that
+ * Lr(p, .) depends on.  cen_base / cen_match [H][W]; base_is_right as in
+ * oracle_cost.  S [D] uint16 (output). */
+void oracle_aggregate_at(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, int D,
+                         int base_is_right, int P1, int P2, unsigned path_mask, int x, int y,
+                         uint16_t *S)
+{
+    int32_t *L = (int32_t *)malloc((size_t)D * sizeof(int32_t));
+    int32_t *Ln = (int32_t *)malloc((size_t)D * sizeof(int32_t));
+    int32_t *acc = (int32_t *)calloc((size_t)D, sizeof(int32_t));
+    for (int r = 0; r < 8; ++r) {
+        if (!(path_mask & (1u << r))) continue;
+        const int rx = ORACLE_DIR[r][0], ry = ORACLE_DIR[r][1];
+        int K = 0;
+        while (x - (K + 1) * rx >= 0 && x - (K + 1) * rx <= W - 1 && y - (K + 1) * ry >= 0 &&
+               y - (K + 1) * ry <= H - 1)
+            ++K;
+        for (int k = K; k >= 0; --k) {
+            const int px = x - k * rx, py = y - k * ry;
+            const uint64_t cb = cen_base[(size_t)py * W + px];
+            int32_t M = 0;
+            if (k < K) {
+                M = L[0];
+                for (int j = 1; j < D; ++j)
+                    if (L[j] < M) M = L[j];
+            }
+            for (int d = 0; d < D; ++d) {
+                const int mx = base_is_right ? px + d : px - d;
+                const int c = (mx < 0 || mx > W - 1)
+                                  ? ORACLE_CMAX
+                                  : popcount64(cb ^ cen_match[(size_t)py * W + mx]);
+                if (k == K) { /* the path enters the image here: Lr = C */
+                    Ln[d] = c;
+                    continue;
+                }
+                int32_t best = L[d];
+                if (d - 1 >= 0 && L[d - 1] + P1 < best) best = L[d - 1] + P1;
+                if (d + 1 <= D - 1 && L[d + 1] + P1 < best) best = L[d + 1] + P1;
+                if (M + P2 < best) best = M + P2;
+                Ln[d] = c + best - M;
+            }
+            memcpy(L, Ln, (size_t)D * sizeof(int32_t));
+        }
+        for (int d = 0; d < D; ++d) acc[d] += L[d];
+    }
+    for (int d = 0; d < D; ++d) S[d] = (uint16_t)acc[d];
+    free(L);
+    free(Ln);
+    free(acc);
+}
+
+/* The plain disparity map (census, left and right aggregation, WTA, sub-pixel,
+ * LR check) at n sampled pixels (xs[i], ys[i]) of one pair: the left view's
+ * S at the pixel and the right view's S at q = x - d*_L.  Outputs per sample:
+ * wta (d*_L), disp (d_sub or -1), valid. */
+void oracle_disparity_at(const uint8_t *left, const uint8_t *right, int H, int W, int pitch, int D,
+                         int P1, int P2, int tol, const int *xs, const int *ys, int n, int16_t *wta,
+                         float *disp, uint8_t *valid)
+{
+    size_t npx = (size_t)H * W;
+    uint64_t *cl = (uint64_t *)malloc(npx * 8), *cr = (uint64_t *)malloc(npx * 8);
+    uint16_t *S = (uint16_t *)malloc((size_t)D * 2);
+    int16_t w1[1];
+    float ds[1];
+    oracle_census(left, H, W, pitch, cl);
+    oracle_census(right, H, W, pitch, cr);
+    for (int i = 0; i < n; ++i) {
+        const int x = xs[i], y = ys[i];
+        oracle_aggregate_at(cl, cr, H, W, D, 0, P1, P2, 0xFFu, x, y, S);
+        oracle_wta(S, 1, 1, D, w1, ds);
+        const int dl = w1[0], q = x - dl;
+        int ok = 0;
+        if (q >= 0) {
+            int16_t wr[1];
+            oracle_aggregate_at(cr, cl, H, W, D, 1, P1, P2, 0xFFu, q, y, S);
+            oracle_wta(S, 1, 1, D, wr, NULL);
+            int diff = dl - wr[0];
+            if (diff < 0) diff = -diff;
+            ok = diff <= tol;
+        }
+        wta[i] = (int16_t)dl;
+        valid[i] = (uint8_t)ok;
+        disp[i] = ok ? ds[0] : -1.0f;
+    }
+    free(cl);
+    free(cr);
+    free(S);
+}

@@ -85,7 +85,7 @@ SIGNATURES = {
     "sf_densify": (I, [P, P, I, I, P, P, P, SZ, P]),
     "sf_temporal_check": (I, [P, P, P, P, I, I, F, F, P, P]),
     "sf_flow_workspace_bytes": (SZ, [I, I, I]),
-    "sf_flow": (I, [P, P, I, I, I, I, I, I, ct.c_uint64, I, P, P, P, P, SZ, P]),
+    "sf_flow": (I, [P, P, I, I, I, I, I, I, I, ct.c_uint64, I, P, P, P, P, SZ, P]),
     "sf_probe_stream": (I, [P, P, SZ, I, P]),
     "sf_probe_pk_u16": (I, [P, I, I, P]),
 }

@@ -236,7 +236,7 @@ def temporal_check(sf4_a, valid_a, sf4_b, valid_b, tau_f: float = 2.0, tau_d: fl
 
 
 def flow(L0, L1, levels: int = 5, iters: int = 6, R: int = 128, seed: int = 1801, tol: int = 1,
-         out=None, stream=None):
+         fine_radius: int = 0, out=None, stream=None):
     """Optical-flow stand-in -> {"flow": [H][W][2] float (NaN where the
     forward-backward check drops it), "F", "B": [H][W][2] int16}."""
     H, W = L0.shape
@@ -254,7 +254,7 @@ def flow(L0, L1, levels: int = 5, iters: int = 6, R: int = 128, seed: int = 1801
     ws = o.get("workspace")
     if ws is None:
         ws = torch.empty(lib().sf_flow_workspace_bytes(H, W, levels), dtype=torch.uint8, device=dev)
-    check(lib().sf_flow(_ptr(L0), _ptr(L1), L0.stride(0), H, W, levels, iters, R, seed, tol, _ptr(F),
+    check(lib().sf_flow(_ptr(L0), _ptr(L1), L0.stride(0), H, W, levels, iters, R, fine_radius, seed, tol, _ptr(F),
                         _ptr(B), _ptr(fl), _ptr(ws), ws.numel(), _stream(stream)))
     return {"flow": fl, "F": F, "B": B, "workspace": ws}
 

@@ -11,7 +11,9 @@
 //     flow whose target leaves the image is no candidate;
 //   * each iteration updates all pixels from the previous field: own f, the f
 //     of the neighbours at distance 1 then 4 (left, right, up, down), then
-//     random search around the best so far with radii R_l >> k, offsets drawn
+//     random search around the best so far with radii R_l >> k (R_l = max(1,
+//     R >> l), capped at fine_radius below the coarsest level when
+//     fine_radius > 0), offsets drawn
 //     from SplitMix64 (counter = (((level*64 + iter)*64 + k)*65536 + y/8)*65536
 //     + x/8: one offset per 8x8 tile, so a wave's candidate loads stay mostly
 //     contiguous); the first candidate with the lowest cost wins;
@@ -70,7 +72,7 @@ __device__ __forceinline__ int flow_cost(const uint64_t (&a)[9], const uint64_t 
 
 __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__restrict__ c0,
                                                              const uint64_t *__restrict__ c1, int H,
-                                                             int W, int level, int iter, int R,
+                                                             int W, int level, int iter, int Rl,
                                                              uint64_t seed,
                                                              const short2 *__restrict__ fin,
                                                              short2 *__restrict__ fout)
@@ -99,6 +101,9 @@ __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__r
             const int ny = y + (n == 2 ? -d : (n == 3 ? d : 0));
             if (nx < 0 || nx > W - 1 || ny < 0 || ny > H - 1) continue;
             const short2 c = fin[(size_t)ny * W + nx];
+            // A candidate equal to the best so far has its cost and cannot win
+            // (only a strictly lower cost replaces): skip its evaluation.
+            if (c.x == bu && c.y == bv) continue;
             const int cc = flow_cost(a, c1, H, W, x, y, c.x, c.y);
             if (cc >= 0 && cc < best) {
                 best = cc;
@@ -107,8 +112,7 @@ __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__r
             }
         }
     }
-    // Random search around the best so far, radii halving.
-    const int Rl = max(1, R >> level);
+    // Random search around the best so far, radii halving from Rl.
     for (int k = 0; (Rl >> k) >= 1; ++k) {
         const int r = Rl >> k;
         const uint64_t ctr =
@@ -119,6 +123,7 @@ __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__r
         const uint32_t m = (uint32_t)(2 * r + 1);
         const int ou = (int)((uint32_t)(h & 0xFFFFu) % m) - r;
         const int ov = (int)((uint32_t)((h >> 16) & 0xFFFFu) % m) - r;
+        if (ou == 0 && ov == 0) continue;  // the best itself: cannot win
         const int cu = bu + ou, cv = bv + ov;
         const int cc = flow_cost(a, c1, H, W, x, y, cu, cv);
         if (cc >= 0 && cc < best) {
@@ -214,8 +219,8 @@ static FlowLayout flow_layout(int H, int W, int levels)
 }
 
 // Integer flow from image s to image 1-s over the prepared pyramid / census.
-static int run_direction(const FlowLayout &L, uint8_t *ws, int s, int iters, int R, uint64_t seed,
-                         short2 *result, hipStream_t st)
+static int run_direction(const FlowLayout &L, uint8_t *ws, int s, int iters, int R, int fine_radius,
+                         uint64_t seed, short2 *result, hipStream_t st)
 {
     short2 *buf[2] = {reinterpret_cast<short2 *>(ws + L.off_f[0]), reinterpret_cast<short2 *>(ws + L.off_f[1])};
     int cur = 0;
@@ -230,8 +235,10 @@ static int run_direction(const FlowLayout &L, uint8_t *ws, int s, int iters, int
         const uint64_t *c0 = reinterpret_cast<const uint64_t *>(ws + L.off_cen[s][l]);
         const uint64_t *c1 = reinterpret_cast<const uint64_t *>(ws + L.off_cen[1 - s][l]);
         dim3 grid((w + FL_T - 1) / FL_T, (h + FL_T - 1) / FL_T);
+        int Rl = max(1, R >> l);
+        if (l < L.levels - 1 && fine_radius > 0 && Rl > fine_radius) Rl = fine_radius;
         for (int it = 0; it < iters; ++it) {
-            hipLaunchKernelGGL(pm_iter_kernel, grid, dim3(FL_T, FL_T), 0, st, c0, c1, h, w, l, it, R, seed,
+            hipLaunchKernelGGL(pm_iter_kernel, grid, dim3(FL_T, FL_T), 0, st, c0, c1, h, w, l, it, Rl, seed,
                                buf[cur], buf[1 - cur]);
             cur = 1 - cur;
         }
@@ -252,8 +259,8 @@ extern "C" size_t sf_flow_workspace_bytes(int H, int W, int levels)
 }
 
 extern "C" int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, int W, int levels,
-                       int iters, int R, uint64_t seed, int tol, int16_t *F, int16_t *B, float *flow,
-                       void *workspace, size_t ws_bytes, void *stream)
+                       int iters, int R, int fine_radius, uint64_t seed, int tol, int16_t *F,
+                       int16_t *B, float *flow, void *workspace, size_t ws_bytes, void *stream)
 {
     clear_error();
     SF_REQUIRE(L0 && L1 && F && B && flow, SF_EINVAL, "sf_flow: NULL pointer");
@@ -262,6 +269,7 @@ extern "C" int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, i
     SF_REQUIRE(levels >= 1 && levels <= FL_MAXLEV, SF_EINVAL, "sf_flow: levels must be in [1, 16]");
     SF_REQUIRE(iters >= 1 && iters <= 63, SF_EINVAL, "sf_flow: iters must be in [1, 63]");
     SF_REQUIRE(R >= 1 && R <= 16383, SF_EINVAL, "sf_flow: R must be in [1, 16383]");
+    SF_REQUIRE(fine_radius >= 0, SF_EINVAL, "sf_flow: fine_radius < 0");
     SF_REQUIRE(tol >= 0, SF_EINVAL, "sf_flow: tol < 0");
     const FlowLayout L = flow_layout(H, W, levels);
     SF_REQUIRE(workspace, SF_EINVAL, "sf_flow: NULL workspace");
@@ -296,8 +304,10 @@ extern "C" int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, i
         ca.W = L.w[l];
         if ((rc = launch_census(ca, st))) return rc;
     }
-    if ((rc = run_direction(L, ws, 0, iters, R, seed, reinterpret_cast<short2 *>(F), st))) return rc;
-    if ((rc = run_direction(L, ws, 1, iters, R, seed ^ 0x5bd1e995ULL, reinterpret_cast<short2 *>(B), st)))
+    if ((rc = run_direction(L, ws, 0, iters, R, fine_radius, seed, reinterpret_cast<short2 *>(F), st)))
+        return rc;
+    if ((rc = run_direction(L, ws, 1, iters, R, fine_radius, seed ^ 0x5bd1e995ULL,
+                            reinterpret_cast<short2 *>(B), st)))
         return rc;
     const int n = H * W;
     hipLaunchKernelGGL(fb_check_kernel, dim3((n + 255) / 256), dim3(256), 0, st,

@@ -41,6 +41,13 @@ __device__ __forceinline__ uint16_t bf16_bits(float f)
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+// The same rounding for a value that is not NaN (a ReLU output): no branch;
+// exact for every other input, infinities included.
+__device__ __forceinline__ uint16_t bf16_bits_nonnan(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
 __device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 __device__ __forceinline__ float bf16_round(float f) { return bf16_val(bf16_bits(f)); }
 
@@ -556,9 +563,9 @@ __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi,
             const int py = mo / wo, px = mo - py * wo;
             const int gy = gy0 + py, gx = gx0 + px;
             float v = acc[i] + bias;
-            v = v > 0.0f ? v : 0.0f;
-            if (gy < 0 || gy >= H || gx < 0 || gx >= W) v = 0.0f;
-            sOut[(py * wo + px) * 16 + n] = bf16_bits(v);
+            const bool inside = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+            v = (v > 0.0f && inside) ? v : 0.0f;  // ReLU (a NaN sum gives 0) and zero padding
+            sOut[mo * 16 + n] = bf16_bits_nonnan(v);
         }
     }
 }
@@ -608,10 +615,17 @@ __global__ __launch_bounds__(256) void lrnet_fused_kernel(const uint2 *__restric
         for (int ky = 0; ky < 3; ++ky)
 #pragma unroll
             for (int kx = 0; kx < 3; ++kx) {
-                const uint16_t *a = sA1 + ((oy + ky) * W3 + ox + kx) * 16;
+                // The 16 channels of one tap as two 16-byte LDS reads; bf16 -> f32
+                // is a shift (even channel) or a mask (odd channel).
+                const uint4 *a = reinterpret_cast<const uint4 *>(sA1 + ((oy + ky) * W3 + ox + kx) * 16);
+                const uint4 lo = a[0], hi = a[1];
+                const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-                for (int ci = 0; ci < 16; ++ci)
-                    acc = __builtin_fmaf(sW4[ci * 9 + ky * 3 + kx], bf16_val(a[ci]), acc);
+                for (int ci = 0; ci < 16; ++ci) {
+                    const uint32_t u = w[ci >> 1];
+                    const float av = __uint_as_float((ci & 1) ? (u & 0xffff0000u) : (u << 16));
+                    acc = __builtin_fmaf(sW4[ci * 9 + ky * 3 + kx], av, acc);
+                }
             }
         logits[img + (size_t)gy * W + gx] = acc + b4;
     }

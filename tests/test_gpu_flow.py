@@ -35,13 +35,14 @@ def check(orc, A, B, **kw):
     assert np.array_equal(host(got["flow"]), out, equal_nan=True)
 
 
-@pytest.mark.parametrize("H,W,levels,iters,R,seed", [
-    (1, 1, 1, 1, 1, 0), (1, 40, 2, 2, 8, 1), (37, 1, 2, 2, 8, 2), (13, 17, 3, 3, 16, 3),
-    (96, 160, 4, 3, 64, 4), (97, 161, 5, 2, 128, 5), (64, 200, 1, 4, 32, 6)])
-def test_flow_small_vs_oracle(orc, H, W, levels, iters, R, seed):
-    say("flow", H, W, levels, iters, R, seed)
+@pytest.mark.parametrize("H,W,levels,iters,R,seed,fine", [
+    (1, 1, 1, 1, 1, 0, 0), (1, 40, 2, 2, 8, 1, 0), (37, 1, 2, 2, 8, 2, 2), (13, 17, 3, 3, 16, 3, 0),
+    (96, 160, 4, 3, 64, 4, 0), (96, 160, 4, 3, 64, 4, 4), (97, 161, 5, 2, 128, 5, 8),
+    (64, 200, 1, 4, 32, 6, 3)])
+def test_flow_small_vs_oracle(orc, H, W, levels, iters, R, seed, fine):
+    say("flow", H, W, levels, iters, R, seed, fine)
     A, B = crop_pair(seed % 3, H, W)
-    check(orc, A, B, levels=levels, iters=iters, R=R, seed=seed, tol=1)
+    check(orc, A, B, levels=levels, iters=iters, R=R, seed=seed, tol=1, fine_radius=fine)
 
 
 def test_flow_pitch_and_tolerance(orc):
@@ -59,20 +60,21 @@ def test_flow_pitch_and_tolerance(orc):
     fl = torch.empty((50, 90, 2), dtype=torch.float32, device=DEV)
     ws = torch.empty(_lib.lib().sf_flow_workspace_bytes(50, 90, 3), dtype=torch.uint8, device=DEV)
     _lib.check(_lib.lib().sf_flow(ct.c_void_p(ta.data_ptr()), ct.c_void_p(tb.data_ptr()), 128, 50, 90, 3, 3,
-                                  32, 77, 0, ct.c_void_p(F.data_ptr()), ct.c_void_p(Bk.data_ptr()),
+                                  32, 4, 77, 0, ct.c_void_p(F.data_ptr()), ct.c_void_p(Bk.data_ptr()),
                                   ct.c_void_p(fl.data_ptr()), ct.c_void_p(ws.data_ptr()), ws.numel(),
                                   ct.c_void_p(torch.cuda.current_stream().cuda_stream)))
     torch.cuda.synchronize()
-    eF, eB, eo = orc.flow(A, B, levels=3, iters=3, R=32, seed=77, tol=0)
+    eF, eB, eo = orc.flow(A, B, levels=3, iters=3, R=32, seed=77, tol=0, fine_radius=4)
     assert np.array_equal(host(F), eF) and np.array_equal(host(Bk), eB)
     assert np.array_equal(host(fl), eo, equal_nan=True)
 
 
-def test_flow_full_size_vs_oracle(orc):
+@pytest.mark.parametrize("fine", [0, 8])
+def test_flow_full_size_vs_oracle(orc, fine):
     """1242x375 frame, 5 levels, 2 iterations per level, R = 128."""
-    say("flow 1242x375 vs oracle")
+    say("flow 1242x375 vs oracle", fine)
     fr = synth.frame_c2(0)
-    check(orc, fr.t0.left, fr.t1.left, levels=5, iters=2, R=128, seed=1801, tol=1)
+    check(orc, fr.t0.left, fr.t1.left, levels=5, iters=2, R=128, seed=1801, tol=1, fine_radius=fine)
 
 
 def test_flow_translation_on_gpu():

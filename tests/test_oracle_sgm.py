@@ -372,3 +372,33 @@ def test_triangulation_closed_forms(orc):
     d0z[0, 0] = 0.0
     sf4, valid, xyz0, motion = orc.combine(d0z, v, d0, v, np.zeros((H, W, 2), np.float32), (f, B, cx, cy))
     assert valid[0, 0] == 1 and np.isnan(xyz0[0, 0]).all() and np.isnan(motion[0, 0]).all()
+
+
+# --- sampled oracle (for images too large for the full oracle) ----------------------------
+
+def test_aggregate_at_equals_full_aggregation(orc):
+    rng = np.random.default_rng(31)
+    H, W, D = 9, 23, 8
+    L = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    R = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    cl, cr = orc.census(L), orc.census(R)
+    for right in (False, True):
+        base, match = (cr, cl) if right else (cl, cr)
+        S = orc.aggregate(orc.cost(base, match, D, right), 10, 40)
+        for y in range(H):
+            for x in range(W):
+                assert np.array_equal(orc.aggregate_at(base, match, D, right, 10, 40, x, y), S[y, x]), (x, y)
+    for mask in (0x01, 0x22, 0xC0):
+        S = orc.aggregate(orc.cost(cl, cr, D, False), 5, 30, mask)
+        assert np.array_equal(orc.aggregate_at(cl, cr, D, False, 5, 30, 11, 4, mask), S[4, 11])
+
+
+def test_disparity_at_equals_full_map(orc):
+    p = synth.pair_c1(2)
+    w, disp, valid = orc.disparity(p.left, p.right, 32)
+    rng = np.random.default_rng(32)
+    ys = rng.integers(0, 96, 60)
+    xs = rng.integers(0, 320, 60)
+    ws, ds, vs = orc.disparity_at(p.left, p.right, 32, xs, ys)
+    assert np.array_equal(ws, w[ys, xs]) and np.array_equal(vs, valid[ys, xs])
+    assert np.array_equal(ds, disp[ys, xs])
