@@ -83,7 +83,7 @@ int sf_cost(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, i
  *   S         [H][W][D] uint16 (output)
  *   workspace device scratch of at least sf_sgm_workspace_bytes(H, W, D) bytes
  * Supported: D a multiple of 32 in [32, 256]; 0 <= P1 <= P2 <= 8000;
- * path_mask in [1, 255].
+ * path_mask in [1, 255]; H * W * D < 2^31 (the kernels use 32-bit offsets).
  * Errors: SF_EINVAL (NULL, H/W <= 0, P2 < P1, P2 > 8000, mask 0 or > 255),
  * SF_EUNSUPPORTED (D), SF_ENOMEM (ws_bytes too small). */
 size_t sf_sgm_workspace_bytes(int H, int W, int D);
@@ -225,7 +225,8 @@ int sf_plan_destroy(sf_plan plan);
  *          SF_FRAME_ADAPTIVE_P2 = intensity-adaptive large-jump penalty in
  *          every aggregation (sf_sgm_aggregate_adaptive; each view's base
  *          image: L0, R0, L1, R1).
- * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535.
+ * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H <= 65535;
+ * H * W * D < 2^31.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (device table upload). */
 #define SF_FRAME_PERSISTENT 1
 #define SF_FRAME_LEARNED 2
@@ -266,7 +267,7 @@ int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, con
  * creation and must stay valid while the plan is used.
  * Tuning of the aggregation per size class (sf_agg_tuning; classes numbered in
  * order of first appearance in `pairs`; NULL / missing = {16, 8, 0, 0}).
- * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255.
+ * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H * W * D < 2^31 per pair.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (table upload). */
 typedef struct {
     int H, W, D, pitch;

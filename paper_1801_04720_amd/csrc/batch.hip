@@ -208,6 +208,8 @@ extern "C" int sf_batch_plan_create(const sf_pair *pairs, int n, int P1, int P2,
         SF_REQUIRE(q.left && q.right && q.disp && q.valid, SF_EINVAL, "sf_batch_plan_create: NULL pointer in a pair");
         SF_REQUIRE(q.H > 0 && q.W > 0 && q.H <= 65535 && (long long)q.H * q.W <= (1LL << 28), SF_EINVAL,
                    "sf_batch_plan_create: pair size out of range");
+        SF_REQUIRE((long long)q.H * q.W * q.D <= 0x7FFFFFFFLL, SF_EINVAL,
+                   "sf_batch_plan_create: H * W * D of a pair must stay below 2^31");
         SF_REQUIRE(q.pitch >= q.W, SF_EINVAL, "sf_batch_plan_create: pitch < W");
         SF_REQUIRE(q.D >= 32 && q.D <= SF_DMAX && q.D % 32 == 0, SF_EUNSUPPORTED,
                    "sf_batch_plan_create: D must be a multiple of 32 in [32, 256]");
@@ -398,6 +400,8 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
     clear_error();
     SF_REQUIRE(best, SF_EINVAL, "sf_agg_autotune: NULL best");
     SF_REQUIRE(H > 0 && W > 0 && (long long)H * W <= (1LL << 28), SF_EINVAL, "sf_agg_autotune: bad size");
+    SF_REQUIRE((long long)H * W * D <= 0x7FFFFFFFLL, SF_EINVAL,
+               "sf_agg_autotune: H * W * D must stay below 2^31");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED, "sf_agg_autotune: bad D");
     SF_REQUIRE(P1 >= 0 && P2 >= P1 && SF_CMAX + P2 <= 255, SF_EINVAL, "sf_agg_autotune: bad P1/P2");
     SF_REQUIRE(nviews >= 1 && nviews <= 8, SF_EINVAL, "sf_agg_autotune: nviews must be in [1, 8]");

@@ -63,6 +63,8 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
     SF_REQUIRE(lr_tol >= 0, SF_EINVAL, "sf_frame_plan_create: lr_tol < 0");
     SF_REQUIRE(D >= 32 && D <= SF_DMAX && D % 32 == 0, SF_EUNSUPPORTED,
                "sf_frame_plan_create: D must be a multiple of 32 in [32, 256]");
+    SF_REQUIRE((long long)H * W * D <= 0x7FFFFFFFLL, SF_EINVAL,
+               "sf_frame_plan_create: H * W * D must stay below 2^31 (32-bit volume offsets)");
     SF_REQUIRE((flags & ~(SF_FRAME_PERSISTENT | SF_FRAME_LEARNED | SF_FRAME_DIAG | SF_FRAME_MEDIAN |
                           SF_FRAME_ADAPTIVE_P2)) == 0,
                SF_EINVAL, "sf_frame_plan_create: unknown flags");

@@ -641,6 +641,8 @@ static int aggregate_impl(const uint8_t *cost, const uint8_t *img, int pitch, in
     SF_REQUIRE(D % 32 == 0, SF_EUNSUPPORTED,
                "sf_sgm_aggregate: these kernels need D to be a multiple of 32");
     SF_REQUIRE((long long)H * W <= (1LL << 28), SF_EINVAL, "sf_sgm_aggregate: image too large");
+    SF_REQUIRE((long long)H * W * D <= 0x7FFFFFFFLL, SF_EINVAL,
+               "sf_sgm_aggregate: H * W * D must stay below 2^31 (32-bit volume offsets)");
     PathTable tab{};
     tab.off[0] = 0;
     for (int r = 0; r < 8; ++r) {

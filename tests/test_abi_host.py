@@ -123,3 +123,13 @@ def test_variant_validation(L):
     expect(L.sf_frame_plan_create(64, 64, 32, 10, 120, 1, 4 | 2, None, ct.byref(plan)), 1, "exclude")
     expect(L.sf_frame_plan_create(64, 5000, 32, 10, 120, 1, 4, None, ct.byref(plan)), 2, "4096")
     expect(L.sf_frame_plan_create(64, 64, 32, 10, 120, 1, 64, None, ct.byref(plan)), 1, "unknown flags")
+
+
+def test_volume_offset_limit(L):
+    # H * W * D must stay below 2^31 for the 32-bit volume offsets of the kernels.
+    plan = ct.c_void_p()
+    expect(L.sf_frame_plan_create(8192, 1024, 256, 10, 120, 1, 0, None, ct.byref(plan)), 1, "2^31")
+    expect(L.sf_sgm_aggregate(FAKE, 8192, 1024, 256, 10, 120, 255, FAKE, FAKE, 1 << 40, None), 1, "2^31")
+    pair = _lib.SfPair(8192, 1024, 256, 1024, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
+    arr = (_lib.SfPair * 1)(pair)
+    expect(L.sf_batch_plan_create(arr, 1, 10, 120, 1, None, 0, 0, ct.byref(plan)), 1, "2^31")
