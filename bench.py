@@ -223,8 +223,11 @@ def bench_stream(args, dev):
     def run_stream(judge_every):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
         agree = []
-        for i, f in enumerate(frames[:2]):  # warm-up
-            (learned if judge_every else plain).run(*f)
+        for i, f in enumerate(frames[:2]):  # warm-up, judge comparison included
+            out = (learned if judge_every else plain).run(*f)
+            if judge_every:
+                ref = plain.run(*f)
+                (out["valid0"] == ref["valid0"]).float().mean().item()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, f in enumerate(frames):
@@ -297,6 +300,29 @@ def bench_stream(args, dev):
     wl, ll, agree = run_stream(16)
     wp, lp, _ = run_stream(0)
     we, le, agree_e = run_stream_from_host(16)
+
+    # Per-kernel times of the plain frame at this size, where the per-pixel
+    # stages are not launch-bound: bytes moved per launch over the time.
+    from paper_1801_04720_amd import _lib
+
+    lib = _lib.lib()
+    nk = 10
+    torch.cuda.synchronize()
+    _lib.check(lib.sf_prof_enable(64 * nk))
+    for f in frames[:nk]:
+        plain.run(*f)
+    torch.cuda.synchronize()
+    lib.sf_prof_disable()
+    npx = H * W
+    moved = {"census": 4 * npx * (1 + 8), "cost": 4 * npx * (16 + D),
+             "sgm_tasks": 4 * npx * D * (8 + 8), "wta_slab_right": 2 * npx * D * 8,
+             "wta_slab_left": 2 * npx * D * 8, "combine": npx * 59}
+    kern = {}
+    for name, nbytes in moved.items():
+        tot, nl = kernel_ms(lib, name)
+        if nl:
+            kern[name] = {"avg_ms": tot / nl, "bytes_per_launch": nbytes,
+                          "TBps": nbytes / (tot / nl * 1e-3) / 1e12}
     res = {
         "metric": "scene-flow stream: sustained fps + p50/p99 per-frame latency @2048x1024 D=256",
         "value": n / wl, "unit": "frames/s", "n_gpus": 1, "steps": n, "warmup": 2,
@@ -316,6 +342,7 @@ def bench_stream(args, dev):
         "judge_mask_agreement_mean": [float(np.mean([a[0] for a in agree])), float(np.mean([a[1] for a in agree]))],
         "judge_mask_agreement_min": [float(np.min([a[0] for a in agree])), float(np.min([a[1] for a in agree]))],
         "judged_frames": len(agree),
+        "plain_frame_kernels_2048x1024": kern,
         "tuning": {"learned_2views": batch.tuning_dict(t2), "plain_4views": batch.tuning_dict(t4)},
     }
     print(json.dumps(res), flush=True)
