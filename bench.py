@@ -42,7 +42,7 @@ def measured_traffic(kernel):
     summary, only if the kernel sources are unchanged since it was taken."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "sgm_tasks_frame_c2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "sgm_tasks_frame_1242x375_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -623,15 +623,16 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default aggregation tuning instead of the autotuner's choice")
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
-                                                    "lrnet_c2.npz"),
+                                                    "lrnet_1242x375.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
-                    help="c2: the 1242x375 D=128 scene-flow frame (default); c3: the uneven "
-                         "batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); c5: a "
-                         "stream of 2048x1024 D=256 frames, learned with a plain judge every 16th")
-    ap.add_argument("--frames", type=int, default=240, help="frames in the c5 stream")
-    ap.add_argument("--pairs", type=int, default=64, help="pairs in the c3 batch")
-    ap.add_argument("--mem-budget-gb", type=float, default=128.0, help="c3 workspace per wave")
+    ap.add_argument("--workload", default="frame", choices=["frame", "batch", "stream"],
+                    help="frame: the 1242x375 D=128 scene-flow frame (default); batch: the "
+                         "uneven batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); "
+                         "stream: 2048x1024 D=256 frames, learned with a plain judge every 16th")
+    ap.add_argument("--frames", type=int, default=240, help="frames in the 2048x1024 stream")
+    ap.add_argument("--pairs", type=int, default=64, help="pairs in the uneven batch")
+    ap.add_argument("--mem-budget-gb", type=float, default=128.0,
+                    help="workspace per wave of the uneven batch")
     ap.add_argument("--peaks", action="store_true",
                     help="only measure the HBM / last-level-cache stream rates and the packed "
                          "16-bit VALU rate, and exit")
@@ -665,12 +666,12 @@ def main():
         print(json.dumps({"copy_bytes": n, "launches": max(args.steps, 1)}), flush=True)
         return
     lib = _lib.lib()
-    if args.workload == "c3":
+    if args.workload == "batch":
         return bench_batch(args, dev)
-    if args.workload == "c5":
+    if args.workload == "stream":
         return bench_stream(args, dev)
     H, W, D = 375, 1242, 128
-    fr = synth.frame_c2(0)
+    fr = synth.frame_1242x375(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     L0, R0, L1, R1, flow = t(fr.t0.left), t(fr.t0.right), t(fr.t1.left), t(fr.t1.right), t(fr.flow)
     api.sgm_set_epilogue(args.epilogue)

@@ -8,7 +8,7 @@ so that both the HIP path and the CPU oracle consume identical bytes.
 Workloads (the paper measures on KITTI Scene Flow frames, which are not
 available here; these stand in for their shape, 1242x375, and nothing more):
 
-* ``pair_c1``: 320x96 random-texture pair, piecewise-constant disparity
+* ``pair_rectangles``: 320x96 random-texture pair, piecewise-constant disparity
   (background 4 plus three rectangles with integer disparities in [0, D)),
   right view formed by shifting left pixels, occlusions filled with noise.
 * ``frame_planar``: a full scene-flow frame (stereo pairs at t0 and t1 plus a
@@ -17,7 +17,9 @@ available here; these stand in for their shape, 1242x375, and nothing more):
   1920x1080 / D=256 and 2048x1024 / D=256.
 
 Random numbers come from ``numpy.random.Generator(PCG64(seed))`` with
-``seed = 1801047200 + 1000 * config + index``.
+``seed = 1801047200 + 1000 * stream + index``, where ``stream`` is a small
+integer that keeps the inputs of different uses (parity pairs, frames, batch
+pairs, training pairs, sequences) apart.
 """
 from __future__ import annotations
 
@@ -28,8 +30,8 @@ import numpy as np
 SEED_BASE = 1801047200
 
 
-def rng_for(config: int, index: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * int(config) + int(index)))
+def rng_for(stream: int, index: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * int(stream) + int(index)))
 
 
 def blurred_texture(rng: np.random.Generator, H: int, W: int) -> np.ndarray:
@@ -74,9 +76,9 @@ def _last_wins(target: np.ndarray, key: np.ndarray) -> tuple[np.ndarray, np.ndar
     return uniq, pos
 
 
-def pair_c1(index: int = 0, H: int = 96, W: int = 320, D: int = 32, config: int = 1) -> StereoPair:
+def pair_rectangles(index: int = 0, H: int = 96, W: int = 320, D: int = 32, stream: int = 1) -> StereoPair:
     """Piecewise-constant disparity pair (the 320x96, D=32 parity workload)."""
-    rng = rng_for(config, index)
+    rng = rng_for(stream, index)
     L = blurred_texture(rng, H, W)
     gt = np.full((H, W), 4, np.int32)
     for _ in range(3):
@@ -361,15 +363,15 @@ def _disc_real(d: np.ndarray) -> np.ndarray:
 # Named workloads ---------------------------------------------------------------
 
 WORKLOADS = {
-    "c1": dict(H=96, W=320, D=32),
-    "c2": dict(H=375, W=1242, D=128, flow_max=100.0),
+    "pair_320x96": dict(H=96, W=320, D=32),
+    "frame_1242x375": dict(H=375, W=1242, D=128, flow_max=100.0),
     "vga": dict(H=480, W=640, D=64, flow_max=100.0),
     "fhd": dict(H=1080, W=1920, D=256, flow_max=100.0),
-    "c5": dict(H=1024, W=2048, D=256, flow_max=200.0),
+    "frame_2048x1024": dict(H=1024, W=2048, D=256, flow_max=200.0),
 }
 
 
-def frame_c2(index: int = 0) -> Frame:
+def frame_1242x375(index: int = 0) -> Frame:
     """1242x375, D=128 scene-flow frame (flow within +-100 px)."""
     return frame_planar(rng_for(2, index), 375, 1242, 128, 100.0)
 

@@ -94,10 +94,10 @@ def test_graph_replays_match_eager():
                 assert np.array_equal(host(o[k]), r[k]), (rep, k)
 
 
-def test_batch_c3_classes_vs_per_pair_path():
+def test_batch_uneven_classes_vs_per_pair_path():
     """The three size classes of the uneven batch (640x480/64, 1242x375/128,
     1920x1080/256), two pairs each, against the per-pair C-ABI path."""
-    say("batch c3 classes")
+    say("uneven batch size classes")
     sizes = [(480, 640, 64), (375, 1242, 128), (1080, 1920, 256)] * 2
     pairs, _ = make_pairs(sizes, cfg=3)
     b = batch.Batch(pairs, mem_budget=16 << 30)

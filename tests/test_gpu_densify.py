@@ -41,9 +41,9 @@ def test_densify_random(orc, H, W, density):
     assert np.array_equal(host(got["sf4"]), out, equal_nan=True)
 
 
-def test_densify_frame_c2(orc):
+def test_densify_frame_1242x375(orc):
     say("densify a 1242x375 D=128 frame")
-    fr = synth.frame_c2(7)
+    fr = synth.frame_1242x375(7)
     ff = FusedFrame(375, 1242, 128, device=DEV)
     got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
     dense = api.densify(got["sf4"], got["valid"])

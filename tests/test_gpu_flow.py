@@ -22,7 +22,7 @@ def say(*a):
 
 
 def crop_pair(seed, H, W):
-    fr = synth.frame_c2(seed)
+    fr = synth.frame_1242x375(seed)
     return (np.ascontiguousarray(fr.t0.left[:H, :W]), np.ascontiguousarray(fr.t1.left[:H, :W]))
 
 
@@ -73,7 +73,7 @@ def test_flow_pitch_and_tolerance(orc):
 def test_flow_full_size_vs_oracle(orc, fine):
     """1242x375 frame, 5 levels, 2 iterations per level, R = 128."""
     say("flow 1242x375 vs oracle", fine)
-    fr = synth.frame_c2(0)
+    fr = synth.frame_1242x375(0)
     check(orc, fr.t0.left, fr.t1.left, levels=5, iters=2, R=128, seed=1801, tol=1, fine_radius=fine)
 
 

@@ -56,18 +56,18 @@ def test_fused_frame_small(orc, H, W, D, persistent):
     check_frame(got, oracle_frame(orc, fr, D, ff.cam))
 
 
-def test_fused_frame_c2_vs_oracle(orc):
+def test_fused_frame_1242x375_vs_oracle(orc):
     say("fused frame 1242x375 D=128 vs oracle")
-    fr = synth.frame_c2(0)
+    fr = synth.frame_1242x375(0)
     ff = FusedFrame(375, 1242, 128, device=DEV)
     got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
     torch.cuda.synchronize()
     check_frame(got, oracle_frame(orc, fr, 128, ff.cam))
 
 
-def test_fused_equals_stagewise_and_persistent_c2():
+def test_fused_equals_stagewise_and_persistent_1242x375():
     say("fused vs per-stage vs persistent, 1242x375 D=128")
-    fr = synth.frame_c2(1)
+    fr = synth.frame_1242x375(1)
     args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
     a = FusedFrame(375, 1242, 128, device=DEV).run(*args)
     a = {k: host(v).copy() for k, v in a.items()}
@@ -172,7 +172,7 @@ def test_gpu_exact_recovery_piecewise_constant(idx):
     from paper_1801_04720_amd import api
 
     say("gpu exact recovery", idx)
-    p = synth.pair_c1(idx)
+    p = synth.pair_rectangles(idx)
     L, R = dev(p.left), dev(p.right)
     cl, cr = api.census(L), api.census(R)
     Sr = api.sgm_aggregate(api.cost(cr, cl, 32, True), 10, 120)
@@ -183,16 +183,16 @@ def test_gpu_exact_recovery_piecewise_constant(idx):
     assert host(out["valid"])[ok].all()
 
 
-def test_learned_frame_network_vs_oracle_c2(orc):
+def test_learned_frame_network_vs_oracle_1242x375(orc):
     """Full-size learned frame: features and logits of the t0 map against the
     oracle's (features bit-exact; logits within BF16 rounding effects; the masks
     agree wherever the oracle's logit is not within 0.05 of zero)."""
     from paper_1801_04720_amd import api, lrnet
 
     say("learned network vs oracle at 1242x375")
-    fr = synth.frame_c2(2)
+    fr = synth.frame_1242x375(2)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    with np.load(os.path.join(root, "paper_1801_04720_amd", "data", "lrnet_c2.npz"), allow_pickle=False) as z:
+    with np.load(os.path.join(root, "paper_1801_04720_amd", "data", "lrnet_1242x375.npz"), allow_pickle=False) as z:
         prm = z["params"].astype(np.float32)
     L, R = dev(fr.t0.left), dev(fr.t0.right)
     cl, cr = api.census(L), api.census(R)

@@ -52,7 +52,7 @@ def test_census_pitch(orc):
 @pytest.mark.parametrize("right", [False, True])
 def test_cost(orc, D, right):
     say("cost", D, right)
-    p = synth.pair_c1(1)
+    p = synth.pair_rectangles(1)
     cl, cr = orc.census(p.left), orc.census(p.right)
     base, match = (cr, cl) if right else (cl, cr)
     got = host(api.cost(dev(base), dev(match), D, right))
@@ -63,7 +63,7 @@ def test_cost(orc, D, right):
 def test_cost_unaligned_output(orc, offset):
     """Output pointers that are not 16-byte aligned take the narrower stores."""
     say("cost unaligned", offset)
-    p = synth.pair_c1(2)
+    p = synth.pair_rectangles(2)
     cl, cr = orc.census(p.left), orc.census(p.right)
     H, W, D = p.left.shape[0], p.left.shape[1], 32
     buf = torch.full((H * W * D + 16,), 255, dtype=torch.uint8, device=DEV)
@@ -125,8 +125,8 @@ def test_aggregate_path_masks(orc, mask):
 
 
 def test_aggregate_c1_pair(orc):
-    say("aggregate c1")
-    p = synth.pair_c1(0)
+    say("aggregate 320x96")
+    p = synth.pair_rectangles(0)
     C = orc.cost(orc.census(p.left), orc.census(p.right), 32, False)
     got = host(api.sgm_aggregate(dev(C), 10, 120), np.uint16)
     assert np.array_equal(got, orc.aggregate(C, 10, 120))
@@ -163,7 +163,7 @@ def test_wta_lr_features(orc, D):
 @pytest.mark.parametrize("tol", [0, 1, 3])
 def test_lr_tolerance(orc, tol):
     say("lr tol", tol)
-    p = synth.pair_c1(2)
+    p = synth.pair_rectangles(2)
     cl, cr = orc.census(p.left), orc.census(p.right)
     Sl = orc.aggregate(orc.cost(cl, cr, 32, False), 10, 120)
     Sr = orc.aggregate(orc.cost(cr, cl, 32, True), 10, 120)

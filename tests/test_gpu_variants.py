@@ -89,7 +89,7 @@ def test_fused_frame_variants_small(orc, diag, median, H, W, D):
 @pytest.mark.parametrize("diag,median", VARIANTS)
 def test_fused_frame_variants_c2_vs_oracle(orc, diag, median):
     say("fused frame variant 1242x375 D=128", diag, median)
-    fr = synth.frame_c2(3)
+    fr = synth.frame_1242x375(3)
     ff = FusedFrame(375, 1242, 128, diag=diag, median=median, device=DEV)
     got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
     torch.cuda.synchronize()
@@ -100,7 +100,7 @@ def test_fused_frame_variants_c2_vs_oracle(orc, diag, median):
 @pytest.mark.parametrize("diag,median", VARIANTS)
 def test_fused_equals_stagewise_variants(diag, median):
     say("fused vs per-stage variant", diag, median)
-    fr = synth.frame_c2(4)
+    fr = synth.frame_1242x375(4)
     args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
     a = FusedFrame(375, 1242, 128, diag=diag, median=median, persistent=True, device=DEV).run(*args)
     a = {k: host(v).copy() for k, v in a.items()}
@@ -140,7 +140,7 @@ def test_diag_right_map_matches_right_pass_without_smoothing(orc):
     """P1 = P2 = 0 on census costs: the diagonal search in S_L equals the right
     view's own WTA wherever q + d stays inside the image for every d."""
     say("diag == right pass at P1 = P2 = 0")
-    p = synth.pair_c1(2)
+    p = synth.pair_rectangles(2)
     D = 32
     L, R = dev(p.left), dev(p.right)
     cl, cr = api.census(L), api.census(R)
@@ -216,7 +216,7 @@ def test_fused_frame_adaptive_small(orc, diag, median, H, W, D):
 
 def test_fused_frame_adaptive_c2_vs_oracle(orc):
     say("fused frame adaptive 1242x375 D=128")
-    fr = synth.frame_c2(5)
+    fr = synth.frame_1242x375(5)
     ff = FusedFrame(375, 1242, 128, adaptive_p2=True, device=DEV)
     got = ff.run(dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow))
     torch.cuda.synchronize()
@@ -226,7 +226,7 @@ def test_fused_frame_adaptive_c2_vs_oracle(orc):
 @pytest.mark.parametrize("diag", [False, True])
 def test_fused_equals_stagewise_adaptive(diag):
     say("fused vs per-stage adaptive", diag)
-    fr = synth.frame_c2(6)
+    fr = synth.frame_1242x375(6)
     args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
     a = FusedFrame(375, 1242, 128, diag=diag, adaptive_p2=True, device=DEV).run(*args)
     a = {k: host(v).copy() for k, v in a.items()}

@@ -171,7 +171,7 @@ def test_network_separates_simple_labels(orc):
     # Sanity of the whole oracle loop: a few hundred Adam steps on a label that is a
     # threshold of one feature drive the loss well below its starting value.
     rng = np.random.default_rng(6)
-    p = synth.pair_c1(0, H=16, W=24, D=8)
+    p = synth.pair_rectangles(0, H=16, W=24, D=8)
     feat = rng.uniform(0, 1, (2, 8, 8, 4)).astype(np.float32)
     label = (feat[..., 2] > 0.5).astype(np.uint8)
     prm = rand_params(rng, 0.2)

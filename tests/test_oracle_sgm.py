@@ -83,7 +83,7 @@ def test_cost_bitcount_and_oob(orc):
 
 
 def test_cost_left_right_relation(orc):
-    p = synth.pair_c1(3)
+    p = synth.pair_rectangles(3)
     cl, cr = orc.census(p.left), orc.census(p.right)
     D = 32
     CL = orc.cost(cl, cr, D, False)
@@ -140,7 +140,7 @@ def test_path_cost_brute_force_dp(orc):
 
 
 def test_path_cost_bound(orc):
-    p = synth.pair_c1(5)
+    p = synth.pair_rectangles(5)
     cl, cr = orc.census(p.left), orc.census(p.right)
     C = orc.cost(cl, cr, 32, False)
     for P1, P2 in [(10, 120), (5, 30), (0, 200)]:
@@ -254,7 +254,7 @@ def clean_interior(p, margin=5):
 
 @pytest.mark.parametrize("idx", [0, 1, 2, 3])
 def test_exact_recovery_piecewise_constant(orc, idx):
-    p = synth.pair_c1(idx)
+    p = synth.pair_rectangles(idx)
     w, disp, valid = orc.disparity(p.left, p.right, 32, 10, 120)
     ok = clean_interior(p)
     assert ok.sum() > 0.5 * ok.size
@@ -394,7 +394,7 @@ def test_aggregate_at_equals_full_aggregation(orc):
 
 
 def test_disparity_at_equals_full_map(orc):
-    p = synth.pair_c1(2)
+    p = synth.pair_rectangles(2)
     w, disp, valid = orc.disparity(p.left, p.right, 32)
     rng = np.random.default_rng(32)
     ys = rng.integers(0, 96, 60)

@@ -109,7 +109,7 @@ def test_diag_equals_right_pass_without_smoothing(orc, D):
     # P1 = P2 = 0: S = 8 C, and the right-base cost C_R(q, d) equals C_L(q + d, d),
     # so the diagonal search in S_L reproduces the right view's own WTA wherever
     # every d keeps q + d inside the image.
-    p = synth.pair_c1(3)
+    p = synth.pair_rectangles(3)
     cl, cr = orc.census(p.left), orc.census(p.right)
     SL = orc.aggregate(orc.cost(cl, cr, D, False), 0, 0)
     SR = orc.aggregate(orc.cost(cr, cl, D, True), 0, 0)
@@ -148,7 +148,7 @@ def test_median_removes_isolated_outlier(orc):
 # --- whole map with variants -----------------------------------------------------------------
 
 def test_disparity_ex_no_flags_is_plain(orc):
-    p = synth.pair_c1(1)
+    p = synth.pair_rectangles(1)
     a = orc.disparity(p.left, p.right, 32)
     b = orc.disparity_ex(p.left, p.right, 32, 0)
     for x, y in zip(a, b):
@@ -156,7 +156,7 @@ def test_disparity_ex_no_flags_is_plain(orc):
 
 
 def test_disparity_ex_median_and_diag_wiring(orc):
-    p = synth.pair_c1(2)
+    p = synth.pair_rectangles(2)
     cl, cr = orc.census(p.left), orc.census(p.right)
     SL = orc.aggregate(orc.cost(cl, cr, 32, False), 10, 120)
     wl, ds = orc.wta(SL)
@@ -167,7 +167,7 @@ def test_disparity_ex_median_and_diag_wiring(orc):
 
 
 def test_disparity_ex_adaptive_uses_each_views_base_image(orc):
-    p = synth.pair_c1(0)
+    p = synth.pair_rectangles(0)
     cl, cr = orc.census(p.left), orc.census(p.right)
     SR = orc.aggregate_adaptive(orc.cost(cr, cl, 32, True), p.right, 10, 120)
     SL = orc.aggregate_adaptive(orc.cost(cl, cr, 32, False), p.left, 10, 120)
@@ -184,7 +184,7 @@ def test_diag_lr_keeps_most_of_the_clean_interior(orc, idx):
     # on piecewise-constant pairs it still keeps nearly all of the clean interior.
     from test_oracle_sgm import clean_interior
 
-    p = synth.pair_c1(idx)
+    p = synth.pair_rectangles(idx)
     w, disp, valid = orc.disparity_ex(p.left, p.right, 32, orc.DIAG)
     ok = clean_interior(p)
     assert np.array_equal(w[ok], p.gt_disp[ok].astype(np.int16))
