@@ -6,51 +6,103 @@
 
 namespace sf {
 
-constexpr int CEN_TW = 64;  // tile width  (one wave per tile row)
-constexpr int CEN_TH = 4;   // tile height (four waves)
-constexpr int CEN_RX = 4;   // window half-width  (9 wide)
-constexpr int CEN_RY = 3;   // window half-height (7 tall)
+constexpr int CEN_PX = 4;                // pixels per thread: one dword of image bytes
+constexpr int CEN_TX = 64;               // threads per tile row (one wave)
+constexpr int CEN_TW = CEN_TX * CEN_PX;  // tile width in pixels
+constexpr int CEN_TH = 4;                // tile rows (four waves)
+constexpr int CEN_RX = 4;                // window half-width  (9 wide)
+constexpr int CEN_RY = 3;                // window half-height (7 tall)
+constexpr int CEN_LW = (CEN_TW + 2 * CEN_RX) / 4;  // LDS row length in dwords
+constexpr int CEN_LH = CEN_TH + 2 * CEN_RY;        // LDS rows
 
-// One thread per pixel; the (TH + 6) x (TW + 8) window of the tile is staged
-// in LDS with clamp-to-edge, coalesced along rows.
-__global__ __launch_bounds__(CEN_TW *CEN_TH) void census_kernel(CensusArgs a)
+// Each thread computes the census of four horizontally adjacent pixels with
+// byte-parallel arithmetic.  For one window offset, the four neighbours form
+// one dword n4 (an alignbyte of the thread's three row dwords) and the four
+// centres another, c4.  v_lerp_u8 averages bytes with a 9-bit intermediate:
+// per byte (c + (255 - n)) >> 1 >= 128 exactly when n < c, so bit 7 of each
+// byte of lerp(c4, ~n4, 0) is the census bit of one pixel.  Those bits are
+// shifted into eight accumulators, one per code byte (byte j of accumulator b
+// is code byte b of pixel j), and a byte transpose at the end assembles the
+// four 62-bit codes.  The (TH + 6) x (TW + 8) window of the tile is staged in
+// LDS with clamp-to-edge.
+__global__ __launch_bounds__(CEN_TX *CEN_TH) void census_kernel(CensusArgs a)
 {
     const int H = a.H, W = a.W, pitch = a.pitch[blockIdx.z];
     const uint8_t *__restrict__ img = a.img[blockIdx.z];
     uint64_t *__restrict__ out = a.out[blockIdx.z];
-    constexpr int LW = CEN_TW + 2 * CEN_RX;
-    constexpr int LH = CEN_TH + 2 * CEN_RY;
-    __shared__ uint8_t tile[LH][LW];
+    __shared__ uint32_t tile[CEN_LH * CEN_LW];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int x0 = blockIdx.x * CEN_TW, y0 = blockIdx.y * CEN_TH;
-    const int tid = ty * CEN_TW + tx;
-    for (int i = tid; i < LH * LW; i += CEN_TW * CEN_TH) {
-        int ly = i / LW, lx = i - ly * LW;
-        int gy = min(max(y0 + ly - CEN_RY, 0), H - 1);
-        int gx = min(max(x0 + lx - CEN_RX, 0), W - 1);
-        tile[ly][lx] = img[(size_t)gy * pitch + gx];
-    }
-    __syncthreads();
-    const int x = x0 + tx, y = y0 + ty;
-    if (x >= W || y >= H) return;
-    const uint32_t c = tile[ty + CEN_RY][tx + CEN_RX];
-    // Neighbours 0..29 fill bits 61..32 (hi word), 30..61 fill bits 31..0.
-    uint32_t hi = 0, lo = 0;
-    int i = 0;
-#pragma unroll
-    for (int dy = -CEN_RY; dy <= CEN_RY; ++dy) {
-#pragma unroll
-        for (int dx = -CEN_RX; dx <= CEN_RX; ++dx) {
-            if (dx == 0 && dy == 0) continue;
-            uint32_t b = tile[ty + CEN_RY + dy][tx + CEN_RX + dx] < c ? 1u : 0u;
-            if (i < 30)
-                hi = (hi << 1) | b;
-            else
-                lo = (lo << 1) | b;
-            ++i;
+    const int tid = ty * CEN_TX + tx;
+    // Tile byte i of LDS row r is image byte (clamp(y0 + r - RY), clamp(x0 - RX + i)).
+    const bool interior = x0 >= CEN_RX && x0 + CEN_TW + CEN_RX <= W &&
+                          ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch) & 3) == 0;
+    if (interior) {
+        for (int i = tid; i < CEN_LH * CEN_LW; i += CEN_TX * CEN_TH) {
+            const int r = i / CEN_LW, c = i - r * CEN_LW;
+            const int gy = min(max(y0 + r - CEN_RY, 0), H - 1);
+            tile[i] = *reinterpret_cast<const uint32_t *>(img + (size_t)gy * pitch + (x0 - CEN_RX) + 4 * c);
+        }
+    } else {
+        uint8_t *tb = reinterpret_cast<uint8_t *>(tile);
+        for (int i = tid; i < CEN_LH * CEN_LW * 4; i += CEN_TX * CEN_TH) {
+            const int r = i / (CEN_LW * 4), c = i - r * (CEN_LW * 4);
+            const int gy = min(max(y0 + r - CEN_RY, 0), H - 1);
+            const int gx = min(max(x0 - CEN_RX + c, 0), W - 1);
+            tb[i] = img[(size_t)gy * pitch + gx];
         }
     }
-    out[(size_t)y * W + x] = ((uint64_t)hi << 32) | lo;
+    __syncthreads();
+    const int x = x0 + CEN_PX * tx, y = y0 + ty;
+    if (x >= W || y >= H) return;
+    // Row dword k of window row r holds bytes x - 4 + 4k .. x - 1 + 4k.
+    uint32_t w[2 * CEN_RY + 1][3];
+#pragma unroll
+    for (int r = 0; r < 2 * CEN_RY + 1; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) w[r][k] = tile[(ty + r) * CEN_LW + tx + k];
+    const uint32_t c4 = w[CEN_RY][1];
+    uint32_t acc[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[b] = 0;
+    // Neighbour k (row-major, centre skipped) is code bit 61 - k.  Visiting k
+    // downwards fills every code byte from its lowest bit up, so each new bit
+    // enters at bit 7 of its byte while the earlier ones move down.
+    int k = 61;
+#pragma unroll
+    for (int dy = CEN_RY; dy >= -CEN_RY; --dy) {
+        const uint32_t n0 = ~w[dy + CEN_RY][0], n1 = ~w[dy + CEN_RY][1], n2 = ~w[dy + CEN_RY][2];
+#pragma unroll
+        for (int dx = CEN_RX; dx >= -CEN_RX; --dx) {
+            if (dx == 0 && dy == 0) continue;
+            const int s = dx + CEN_RX;  // byte offset of the neighbours within x - 4 .. x + 7
+            const uint32_t lo = s < 4 ? n0 : s < 8 ? n1 : n2, hi = s < 4 ? n1 : n2;
+            const uint32_t nn = (s & 3) == 0 ? lo : (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * (s & 3)));
+            const uint32_t t = __builtin_amdgcn_lerp(c4, nn, 0u);
+            const int b = (61 - k) >> 3;
+            acc[b] = (t & 0x80808080u) | ((acc[b] >> 1) & 0x7f7f7f7fu);
+            --k;
+        }
+    }
+    acc[7] = (acc[7] >> 2) & 0x3f3f3f3fu;  // bits 56..61 of the code; 62 and 63 are zero
+    uint32_t lo[CEN_PX], hi[CEN_PX];
+#pragma unroll
+    for (int j = 0; j < CEN_PX; ++j) {
+        const int sh = 8 * j;
+        lo[j] = ((acc[0] >> sh) & 0xffu) | (((acc[1] >> sh) & 0xffu) << 8) |
+                (((acc[2] >> sh) & 0xffu) << 16) | (((acc[3] >> sh) & 0xffu) << 24);
+        hi[j] = ((acc[4] >> sh) & 0xffu) | (((acc[5] >> sh) & 0xffu) << 8) |
+                (((acc[6] >> sh) & 0xffu) << 16) | (((acc[7] >> sh) & 0xffu) << 24);
+    }
+    uint64_t *o = out + (size_t)y * W + x;
+    if (x + CEN_PX <= W && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+        reinterpret_cast<uint4 *>(o)[0] = make_uint4(lo[0], hi[0], lo[1], hi[1]);
+        reinterpret_cast<uint4 *>(o)[1] = make_uint4(lo[2], hi[2], lo[3], hi[3]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < CEN_PX; ++j)
+            if (x + j < W) o[j] = ((uint64_t)hi[j] << 32) | lo[j];
+    }
 }
 
 constexpr int COST_TP = 64;   // pixels of one row per block
@@ -219,7 +271,7 @@ int launch_census(const CensusArgs &a, hipStream_t st)
 {
     dim3 grid((a.W + CEN_TW - 1) / CEN_TW, (a.H + CEN_TH - 1) / CEN_TH, a.n);
     ProfScope prof("census", st);
-    hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TW, CEN_TH), 0, st, a);
+    hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TX, CEN_TH), 0, st, a);
     return launch_status("census_kernel");
 }
 
