@@ -476,30 +476,51 @@ __global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *
 // Output tile FT_H x FT_W; the layer inputs are kept on halos shrinking by one
 // pixel per layer (features 24 x 40, a1 22 x 38, a2 20 x 36, a3 18 x 34).  Pixels
 // of a halo that fall outside the image hold 0 (zero padding of every layer).
-// Layers 1-3 run on v_mfma_f32_16x16x16_bf16 over groups of 16 consecutive
-// pixels of a region (row-major); layer 1 packs 4 taps x 4 channels per K = 16
-// chunk (3 chunks, the last padded with zero weights); layer 4 is VALU.
+// All four layers run on v_mfma_f32_16x16x16_bf16 over groups of 16
+// consecutive pixels of a region (row-major).  The weights are the A operand
+// (rows = output channels) and the activations the B operand (columns =
+// pixels), so each lane ends up holding four consecutive output channels of
+// one pixel.  Its accumulator starts at the four biases; the epilogue applies
+// ReLU and zero padding, rounds to BF16 (v_cvt_pk_bf16_f32, round to nearest
+// even) and stores the four channels with one 8-byte LDS write.  Layer 1 packs
+// 4 taps x 4 channels per K = 16 chunk (3 chunks, the last padded with zero
+// weights).  Layer 4 (one output channel) puts its 9 taps on the rows of A:
+// one MFMA per 16 pixels gives the per-tap channel sums P_t(p), which go to
+// LDS, and the logit at p is b4 + sum over taps t of P_t(p + offset_t).
 // Weight fragments come pre-packed per lane (pack_fused_kernel).
 constexpr int FT_H = 16, FT_W = 32;
-constexpr int FP_L1 = 0, FP_L2 = 3 * 64, FP_L3 = 12 * 64, FP_FRAGS = 21 * 64;  // uint2 slots
-constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_W4 = 48, FP_B4 = 192, FP_FLOATS = 193;
+constexpr int FT_NW = 16;  // waves per block: they share the tile's LDS, so more of them hide latency
+constexpr int FP_L1 = 0, FP_L2 = 3 * 64, FP_L3 = 12 * 64, FP_L4 = 21 * 64,
+              FP_FRAGS = 22 * 64;  // uint2 slots
+constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_B4 = 48, FP_FLOATS = 49;
+
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values that are not NaN -> packed BF16 (low half = a), round to nearest even.
+__device__ __forceinline__ uint32_t bf16x2_bits(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2v));
+}
 
 __global__ void pack_fused_kernel(const float *__restrict__ prm, uint2 *__restrict__ frag,
                                   float *__restrict__ fl)
 {
     const int lane = threadIdx.x & 63;
-    const int slot = blockIdx.x;  // 0..20
+    const int slot = blockIdx.x;  // 0..21
     const int n = lane & 15, kg = lane >> 4;
     uint16_t h[4];
     for (int i = 0; i < 4; ++i) {
         float w = 0.0f;
-        if (slot < 3) {  // layer 1: tap 4 * slot + kg, channel i
+        if (slot < 3) {  // layer 1: output channel n, tap 4 * slot + kg, input channel i
             const int t = 4 * slot + kg;
             if (t < 9) w = prm[OFF_W1 + (n * 4 + i) * 9 + t];
-        } else {
+        } else if (slot < 21) {  // layers 2, 3: output channel n, tap t, input channel 4 kg + i
             const int t = (slot - 3) % 9;
             const int off = slot < 12 ? OFF_W2 : OFF_W3;
             w = prm[off + (n * 16 + 4 * kg + i) * 9 + t];
+        } else if (n < 9) {  // layer 4: row n = tap n, input channel 4 kg + i
+            w = prm[OFF_W4 + (4 * kg + i) * 9 + n];
         }
         h[i] = bf16_bits(w);
     }
@@ -511,83 +532,93 @@ __global__ void pack_fused_kernel(const float *__restrict__ prm, uint2 *__restri
             if (i < 16) v = prm[OFF_B1 + i];
             else if (i < 32) v = prm[OFF_B2 + i - 16];
             else if (i < 48) v = prm[OFF_B3 + i - 32];
-            else if (i < 192) v = bf16_round(prm[OFF_W4 + i - 48]);
             else v = prm[OFF_B4];
             fl[i] = v;
         }
     }
 }
 
-// One MFMA layer over a region: input sIn [hi][wi][C] (bf16), output sOut [hi-2][wi-2][16];
-// (gy0, gx0) = image coordinates of the output region's first pixel.
+// Offset (in BF16 elements) of channels 4 kg .. 4 kg + 3 of pixel p in a
+// 16-channel activation array.  A pixel takes 32 bytes, so the 8-byte reads of
+// one channel block by 16 consecutive pixels would meet in the same LDS banks;
+// the four blocks are XOR-swizzled by bits 2..3 of p, which spreads them.
+__device__ __forceinline__ int act_off(int p, int kg) { return p * 16 + 4 * (kg ^ ((p >> 2) & 3)); }
+
+// One MFMA layer over a region: input sIn [hi][wi][C] (bf16), output sOut
+// [hi-2][wi-2][16]; (gy0, gx0) = image coordinates of the output region's first
+// pixel; bias = the biases of output channels 4 kg .. 4 kg + 3.
 template <int C, int NCH>
 __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi, uint16_t *sOut,
-                                            const uint2 *__restrict__ frag, float bias, int gy0,
+                                            const uint2 *__restrict__ frag, f32x4 bias, int gy0,
                                             int gx0, int H, int W, int lane, int wave)
 {
     const int ho = hi - 2, wo = wi - 2, nout = ho * wo;
     const int n = lane & 15, kg = lane >> 4;
     bf16x4 bw[NCH];
 #pragma unroll
+    for (int c = 0; c < NCH; ++c) bw[c] = __builtin_bit_cast(bf16x4, frag[c * 64 + lane]);
+    // Layer 1: chunk c of lane kg is tap 4 c + kg (none past tap 8).
+    int toff[NCH];
+#pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        const uint2 f = frag[c * 64 + lane];
-        bw[c] = __builtin_bit_cast(bf16x4, f);
+        const int t = 4 * c + kg;
+        toff[c] = C == 16 ? ((c / 3) * wi + c % 3) * 16 : (t < 9 ? ((t / 3) * wi + t % 3) * 4 : -1);
     }
+    // Zero padding is needed only where the output region reaches outside the image.
+    const bool interior = gy0 >= 0 && gx0 >= 0 && gy0 + ho <= H && gx0 + wo <= W;
     const int ngroups = (nout + 15) >> 4;
-    for (int g = wave; g < ngroups; g += 4) {
-        int m = g * 16 + n;
-        if (m >= nout) m = nout - 1;
+    for (int g = wave; g < ngroups; g += FT_NW) {
+        const int mo = g * 16 + n;
+        const int m = mo < nout ? mo : nout - 1;
         const int oy = m / wo, ox = m - oy * wo;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const int p0 = oy * wi + ox;
+        const uint16_t *src = sIn + p0 * C;
+        // All LDS reads of the group are issued before the MFMA chain uses any.
+        bf16x4 a[NCH];
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            bf16x4 a;
-            if (C == 16) {
-                const int ky = c / 3, kx = c % 3;
-                a = *reinterpret_cast<const bf16x4 *>(sIn + (((oy + ky) * wi + ox + kx) * 16 + 4 * kg));
-            } else {
-                const int t = 4 * c + kg;
-                if (t < 9) {
-                    const int ky = t / 3, kx = t % 3;
-                    a = *reinterpret_cast<const bf16x4 *>(sIn + (((oy + ky) * wi + ox + kx) * 4));
-                } else {
-                    a = bf16x4{0, 0, 0, 0};
-                }
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[c], acc, 0, 0, 0);
+            a[c] = bf16x4{0, 0, 0, 0};
+            if (C == 16)
+                a[c] = *reinterpret_cast<const bf16x4 *>(sIn + act_off(p0 + (c / 3) * wi + c % 3, kg));
+            else if (toff[c] >= 0)
+                a[c] = *reinterpret_cast<const bf16x4 *>(src + toff[c]);
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the chain
+        f32x4 acc = bias;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int mo = g * 16 + 4 * kg + i;
-            if (mo >= nout) continue;
-            const int py = mo / wo, px = mo - py * wo;
-            const int gy = gy0 + py, gx = gx0 + px;
-            float v = acc[i] + bias;
-            const bool inside = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-            v = (v > 0.0f && inside) ? v : 0.0f;  // ReLU (a NaN sum gives 0) and zero padding
-            sOut[mo * 16 + n] = bf16_bits_nonnan(v);
+        for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bw[c], a[c], acc, 0, 0, 0);
+        if (mo >= nout) continue;
+        bool inside = interior;
+        if (!interior) {
+            const int gy = gy0 + oy, gx = gx0 + ox;
+            inside = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
         }
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = (acc[i] > 0.0f && inside) ? acc[i] : 0.0f;  // ReLU (NaN -> 0), padding
+        *reinterpret_cast<uint2 *>(sOut + act_off(mo, kg)) = make_uint2(bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3]));
     }
 }
 
-__global__ __launch_bounds__(256) void lrnet_fused_kernel(const uint2 *__restrict__ frag,
-                                                          const float *__restrict__ fl,
-                                                          const float4 *__restrict__ feat, int H,
-                                                          int W, float *__restrict__ logits)
+__global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint2 *__restrict__ frag,
+                                                                 const float *__restrict__ fl,
+                                                                 const float4 *__restrict__ feat,
+                                                                 int H, int W, float *__restrict__ logits)
 {
     constexpr int FH = FT_H + 8, FW = FT_W + 8;   // features
     constexpr int H1 = FT_H + 6, W1 = FT_W + 6;   // a1
     constexpr int H2 = FT_H + 4, W2 = FT_W + 4;   // a2
     constexpr int H3 = FT_H + 2, W3 = FT_W + 2;   // a3 (aliases a1)
+    constexpr int N3 = H3 * W3;                   // a3 pixels; P (9 x N3 FP32) aliases a2
+    static_assert(9 * N3 * 4 <= H2 * W2 * 16 * 2, "tap sums must fit the a2 buffer");
     __shared__ __align__(16) uint16_t sF[FH * FW * 4];
     __shared__ __align__(16) uint16_t sA1[H1 * W1 * 16];
     __shared__ __align__(16) uint16_t sA2[H2 * W2 * 16];
-    __shared__ float sW4[144];
     const int b = blockIdx.z;
     const int x0 = blockIdx.x * FT_W, y0 = blockIdx.y * FT_H;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const size_t img = (size_t)b * H * W;
-    for (int i = tid; i < FH * FW; i += 256) {
+    for (int i = tid; i < FH * FW; i += 64 * FT_NW) {
         const int ly = i / FW, lx = i - ly * FW;
         const int gy = y0 + ly - 4, gx = x0 + lx - 4;
         float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -596,38 +627,40 @@ __global__ __launch_bounds__(256) void lrnet_fused_kernel(const uint2 *__restric
             make_uint2((uint32_t)bf16_bits(f.x) | ((uint32_t)bf16_bits(f.y) << 16),
                        (uint32_t)bf16_bits(f.z) | ((uint32_t)bf16_bits(f.w) << 16));
     }
-    for (int i = tid; i < 144; i += 256) sW4[i] = fl[FP_W4 + i];
     __syncthreads();
-    const int n = lane & 15;
-    fused_layer<4, 3>(sF, FH, FW, sA1, frag + FP_L1, fl[FP_B1 + n], y0 - 3, x0 - 3, H, W, lane, wave);
+    const int n = lane & 15, kg = lane >> 4;
+    auto bias4 = [&](int off) { return f32x4{fl[off + 4 * kg], fl[off + 4 * kg + 1], fl[off + 4 * kg + 2], fl[off + 4 * kg + 3]}; };
+    fused_layer<4, 3>(sF, FH, FW, sA1, frag + FP_L1, bias4(FP_B1), y0 - 3, x0 - 3, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16, 9>(sA1, H1, W1, sA2, frag + FP_L2, fl[FP_B2 + n], y0 - 2, x0 - 2, H, W, lane, wave);
+    fused_layer<16, 9>(sA1, H1, W1, sA2, frag + FP_L2, bias4(FP_B2), y0 - 2, x0 - 2, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16, 9>(sA2, H2, W2, sA1, frag + FP_L3, fl[FP_B3 + n], y0 - 1, x0 - 1, H, W, lane, wave);
+    fused_layer<16, 9>(sA2, H2, W2, sA1, frag + FP_L3, bias4(FP_B3), y0 - 1, x0 - 1, H, W, lane, wave);
     __syncthreads();
+    // Layer 4, step 1: P[t][p] = sum over the 16 channels of W4[c][t] a3[p][c], tap-major in a2's buffer.
+    float *P = reinterpret_cast<float *>(sA2);
+    const bf16x4 w4 = __builtin_bit_cast(bf16x4, frag[FP_L4 + lane]);
+    for (int g = wave; g < (N3 + 15) / 16; g += FT_NW) {
+        const int p = g * 16 + n;
+        const int pc = p < N3 ? p : N3 - 1;
+        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(sA1 + act_off(pc, kg));
+        const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w4, a, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        if (p < N3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * kg + i < 9) P[(4 * kg + i) * N3 + p] = acc[i];
+        }
+    }
+    __syncthreads();
+    // Step 2: the logit sums the nine tap sums in tap order, then adds the bias.
     const float b4 = fl[FP_B4];
-    for (int p = tid; p < FT_H * FT_W; p += 256) {
-        const int oy = p / FT_W, ox = p - oy * FT_W;
+    for (int q = tid; q < FT_H * FT_W; q += 64 * FT_NW) {
+        const int oy = q / FT_W, ox = q - oy * FT_W;
         const int gy = y0 + oy, gx = x0 + ox;
         if (gy >= H || gx >= W) continue;
-        float acc = 0.0f;
+        float s = 0.0f;
 #pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-#pragma unroll
-            for (int kx = 0; kx < 3; ++kx) {
-                // The 16 channels of one tap as two 16-byte LDS reads; bf16 -> f32
-                // is a shift (even channel) or a mask (odd channel).
-                const uint4 *a = reinterpret_cast<const uint4 *>(sA1 + ((oy + ky) * W3 + ox + kx) * 16);
-                const uint4 lo = a[0], hi = a[1];
-                const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-#pragma unroll
-                for (int ci = 0; ci < 16; ++ci) {
-                    const uint32_t u = w[ci >> 1];
-                    const float av = __uint_as_float((ci & 1) ? (u & 0xffff0000u) : (u << 16));
-                    acc = __builtin_fmaf(sW4[ci * 9 + ky * 3 + kx], av, acc);
-                }
-            }
-        logits[img + (size_t)gy * W + gx] = acc + b4;
+        for (int t = 0; t < 9; ++t) s += P[t * N3 + (oy + t / 3) * W3 + ox + t % 3];
+        logits[img + (size_t)gy * W + gx] = s + b4;
     }
 }
 
@@ -733,9 +766,9 @@ int lrnet_forward(const float *params, const float *feat, int B, int H, int W, f
     uint2 *frag = reinterpret_cast<uint2 *>(ws + L.frag);
     float *fl = reinterpret_cast<float *>(ws + L.fl);
     ProfScope prof("lrnet_fused", st);
-    hipLaunchKernelGGL(pack_fused_kernel, dim3(21), dim3(64), 0, st, params, frag, fl);
+    hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_FRAGS / 64), dim3(64), 0, st, params, frag, fl);
     dim3 g((W + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H, B);
-    hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(256), 0, st, frag, fl,
+    hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(64 * FT_NW), 0, st, frag, fl,
                        reinterpret_cast<const float4 *>(feat), H, W, logits);
     return launch_status("lrnet_fused_kernel");
 }
