@@ -476,25 +476,31 @@ __global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *
 // Output tile FT_H x FT_W; the layer inputs are kept on halos shrinking by one
 // pixel per layer (features 24 x 40, a1 22 x 38, a2 20 x 36, a3 18 x 34).  Pixels
 // of a halo that fall outside the image hold 0 (zero padding of every layer).
-// All four layers run on v_mfma_f32_16x16x16_bf16 over groups of 16
-// consecutive pixels of a region (row-major).  The weights are the A operand
-// (rows = output channels) and the activations the B operand (columns =
-// pixels), so each lane ends up holding four consecutive output channels of
-// one pixel.  Its accumulator starts at the four biases; the epilogue applies
-// ReLU and zero padding, rounds to BF16 (v_cvt_pk_bf16_f32, round to nearest
-// even) and stores the four channels with one 8-byte LDS write.  Layer 1 packs
-// 4 taps x 4 channels per K = 16 chunk (3 chunks, the last padded with zero
-// weights).  Layer 4 (one output channel) puts its 9 taps on the rows of A:
-// one MFMA per 16 pixels gives the per-tap channel sums P_t(p), which go to
-// LDS, and the logit at p is b4 + sum over taps t of P_t(p + offset_t).
-// Weight fragments come pre-packed per lane (pack_fused_kernel).
+// All four layers run on MFMA over groups of 16 consecutive pixels of a region
+// (row-major).  The weights are the A operand (rows = output channels) and the
+// activations the B operand (columns = pixels), so each lane ends up holding
+// four consecutive output channels of one pixel.  Its accumulator starts at
+// the four biases; the epilogue applies ReLU and zero padding, rounds to BF16
+// (v_cvt_pk_bf16_f32, round to nearest even) and stores the four channels with
+// one 8-byte LDS write.  A 3x3 layer with 16 input channels takes five
+// v_mfma_f32_16x16x32_bf16: lane group kg contributes channels 4kg..4kg+3 of
+// the taps (0,1), (2,3), (4,5), (6,7), then of tap 8 with a zero upper half.
+// Layer 1 (4 channels) takes two: taps kg and kg + 4, then tap 8 (group 0).
+// The contraction pairs the elements of A and B by lane group and position, so
+// any consistent assignment of (tap, channel) to positions gives the same sum
+// of products, and one chain uses one MFMA opcode.  Layer 4 (one output
+// channel) puts its 9 taps on the rows of A: one MFMA per 16 pixels gives the
+// per-tap channel sums P_t(p), which go to LDS, and the logit at p is
+// b4 + sum over taps t of P_t(p + offset_t).  Weight fragments come pre-packed
+// per lane (pack_fused_kernel), 16 bytes per lane and slot.
 constexpr int FT_H = 16, FT_W = 32;
 constexpr int FT_NW = 16;  // waves per block: they share the tile's LDS, so more of them hide latency
-constexpr int FP_L1 = 0, FP_L2 = 3 * 64, FP_L3 = 12 * 64, FP_L4 = 21 * 64,
-              FP_FRAGS = 22 * 64;  // uint2 slots
+constexpr int FP_L1 = 0, FP_L2 = 2, FP_L3 = 7, FP_L4 = 12, FP_NSLOT = 13;  // uint4 slots of 64 lanes
+constexpr int FP_FRAGS = FP_NSLOT * 64;
 constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_B4 = 48, FP_FLOATS = 49;
 
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // Two FP32 values that are not NaN -> packed BF16 (low half = a), round to nearest even.
@@ -503,29 +509,35 @@ __device__ __forceinline__ uint32_t bf16x2_bits(float a, float b)
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2v));
 }
 
-__global__ void pack_fused_kernel(const float *__restrict__ prm, uint2 *__restrict__ frag,
+// Pixel offset of tap t (row-major over the 3x3 window) in a region of width wi.
+__device__ __forceinline__ int tap_off(int t, int wi) { return (t / 3) * wi + t % 3; }
+
+__global__ void pack_fused_kernel(const float *__restrict__ prm, uint4 *__restrict__ frag,
                                   float *__restrict__ fl)
 {
     const int lane = threadIdx.x & 63;
-    const int slot = blockIdx.x;  // 0..21
+    const int slot = blockIdx.x;  // 0 .. FP_NSLOT - 1
     const int n = lane & 15, kg = lane >> 4;
-    uint16_t h[4];
-    for (int i = 0; i < 4; ++i) {
+    uint16_t h[8];
+    for (int j = 0; j < 8; ++j) {
+        const int i = j & 3, hi = j >> 2;
         float w = 0.0f;
-        if (slot < 3) {  // layer 1: output channel n, tap 4 * slot + kg, input channel i
-            const int t = 4 * slot + kg;
-            if (t < 9) w = prm[OFF_W1 + (n * 4 + i) * 9 + t];
-        } else if (slot < 21) {  // layers 2, 3: output channel n, tap t, input channel 4 kg + i
-            const int t = (slot - 3) % 9;
-            const int off = slot < 12 ? OFF_W2 : OFF_W3;
-            w = prm[off + (n * 16 + 4 * kg + i) * 9 + t];
-        } else if (n < 9) {  // layer 4: row n = tap n, input channel 4 kg + i
+        if (slot == FP_L1) {  // layer 1, taps kg and kg + 4, input channel i
+            w = prm[OFF_W1 + (n * 4 + i) * 9 + kg + 4 * hi];
+        } else if (slot == FP_L1 + 1) {  // layer 1, tap 8 (lane group 0 only)
+            if (kg == 0 && !hi) w = prm[OFF_W1 + (n * 4 + i) * 9 + 8];
+        } else if (slot < FP_L4) {  // layers 2, 3: taps 2q, 2q + 1 (q < 4) or tap 8, channel 4 kg + i
+            const int q = (slot - FP_L2) % 5;
+            const int off = slot < FP_L3 ? OFF_W2 : OFF_W3;
+            if (q < 4) w = prm[off + (n * 16 + 4 * kg + i) * 9 + 2 * q + hi];
+            else if (!hi) w = prm[off + (n * 16 + 4 * kg + i) * 9 + 8];
+        } else if (n < 9 && !hi) {  // layer 4: row n = tap n, input channel 4 kg + i
             w = prm[OFF_W4 + (4 * kg + i) * 9 + n];
         }
-        h[i] = bf16_bits(w);
+        h[j] = bf16_bits(w);
     }
-    frag[slot * 64 + lane] = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
-                                        (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    frag[slot * 64 + lane] = make_uint4((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+                                        (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16));
     if (slot == 0) {
         for (int i = lane; i < FP_FLOATS; i += 64) {
             float v;
@@ -544,49 +556,54 @@ __global__ void pack_fused_kernel(const float *__restrict__ prm, uint2 *__restri
 // the four blocks are XOR-swizzled by bits 2..3 of p, which spreads them.
 __device__ __forceinline__ int act_off(int p, int kg) { return p * 16 + 4 * (kg ^ ((p >> 2) & 3)); }
 
-// One MFMA layer over a region: input sIn [hi][wi][C] (bf16), output sOut
-// [hi-2][wi-2][16]; (gy0, gx0) = image coordinates of the output region's first
-// pixel; bias = the biases of output channels 4 kg .. 4 kg + 3.
-template <int C, int NCH>
+__device__ __forceinline__ bf16x8 join8(uint2 lo, uint2 hi)
+{
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
+// One 3x3 MFMA layer over a region: input sIn [hi][wi][C] (bf16; C = 16 arrays
+// swizzled by act_off), output sOut [hi-2][wi-2][16] (swizzled); (gy0, gx0) =
+// image coordinates of the output region's first pixel; bias = the biases of
+// output channels 4 kg .. 4 kg + 3; frag = the layer's first weight slot.
+template <int C>
 __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi, uint16_t *sOut,
-                                            const uint2 *__restrict__ frag, f32x4 bias, int gy0,
+                                            const uint4 *__restrict__ frag, f32x4 bias, int gy0,
                                             int gx0, int H, int W, int lane, int wave)
 {
+    constexpr int NQ = C == 16 ? 5 : 2;  // K = 32 MFMAs; the last one holds tap 8 and zeros
     const int ho = hi - 2, wo = wi - 2, nout = ho * wo;
     const int n = lane & 15, kg = lane >> 4;
-    bf16x4 bw[NCH];
+    bf16x8 w32[NQ];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) bw[c] = __builtin_bit_cast(bf16x4, frag[c * 64 + lane]);
-    // Layer 1: chunk c of lane kg is tap 4 c + kg (none past tap 8).
-    int toff[NCH];
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int t = 4 * c + kg;
-        toff[c] = C == 16 ? ((c / 3) * wi + c % 3) * 16 : (t < 9 ? ((t / 3) * wi + t % 3) * 4 : -1);
-    }
+    for (int q = 0; q < NQ; ++q) w32[q] = __builtin_bit_cast(bf16x8, frag[q * 64 + lane]);
     // Zero padding is needed only where the output region reaches outside the image.
     const bool interior = gy0 >= 0 && gx0 >= 0 && gy0 + ho <= H && gx0 + wo <= W;
     const int ngroups = (nout + 15) >> 4;
+    const uint2 zero2 = make_uint2(0u, 0u);
     for (int g = wave; g < ngroups; g += FT_NW) {
         const int mo = g * 16 + n;
         const int m = mo < nout ? mo : nout - 1;
         const int oy = m / wo, ox = m - oy * wo;
         const int p0 = oy * wi + ox;
-        const uint16_t *src = sIn + p0 * C;
         // All LDS reads of the group are issued before the MFMA chain uses any.
-        bf16x4 a[NCH];
+        bf16x8 b32[NQ];
+        if (C == 16) {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            a[c] = bf16x4{0, 0, 0, 0};
-            if (C == 16)
-                a[c] = *reinterpret_cast<const bf16x4 *>(sIn + act_off(p0 + (c / 3) * wi + c % 3, kg));
-            else if (toff[c] >= 0)
-                a[c] = *reinterpret_cast<const bf16x4 *>(src + toff[c]);
+            for (int q = 0; q < 4; ++q)
+                b32[q] = join8(*reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(2 * q, wi), kg)),
+                               *reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(2 * q + 1, wi), kg)));
+            b32[4] = join8(*reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(8, wi), kg)), zero2);
+        } else {
+            b32[0] = join8(*reinterpret_cast<const uint2 *>(sIn + (p0 + tap_off(kg, wi)) * 4),
+                           *reinterpret_cast<const uint2 *>(sIn + (p0 + tap_off(kg + 4, wi)) * 4));
+            uint2 t8 = zero2;
+            if (kg == 0) t8 = *reinterpret_cast<const uint2 *>(sIn + (p0 + tap_off(8, wi)) * 4);
+            b32[1] = join8(t8, zero2);
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the chain
         f32x4 acc = bias;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bw[c], a[c], acc, 0, 0, 0);
+        for (int q = 0; q < NQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w32[q], b32[q], acc, 0, 0, 0);
         if (mo >= nout) continue;
         bool inside = interior;
         if (!interior) {
@@ -600,7 +617,7 @@ __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi,
     }
 }
 
-__global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint2 *__restrict__ frag,
+__global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__restrict__ frag,
                                                                  const float *__restrict__ fl,
                                                                  const float4 *__restrict__ feat,
                                                                  int H, int W, float *__restrict__ logits)
@@ -630,15 +647,16 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint2 *__
     __syncthreads();
     const int n = lane & 15, kg = lane >> 4;
     auto bias4 = [&](int off) { return f32x4{fl[off + 4 * kg], fl[off + 4 * kg + 1], fl[off + 4 * kg + 2], fl[off + 4 * kg + 3]}; };
-    fused_layer<4, 3>(sF, FH, FW, sA1, frag + FP_L1, bias4(FP_B1), y0 - 3, x0 - 3, H, W, lane, wave);
+    fused_layer<4>(sF, FH, FW, sA1, frag + FP_L1 * 64, bias4(FP_B1), y0 - 3, x0 - 3, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16, 9>(sA1, H1, W1, sA2, frag + FP_L2, bias4(FP_B2), y0 - 2, x0 - 2, H, W, lane, wave);
+    fused_layer<16>(sA1, H1, W1, sA2, frag + FP_L2 * 64, bias4(FP_B2), y0 - 2, x0 - 2, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16, 9>(sA2, H2, W2, sA1, frag + FP_L3, bias4(FP_B3), y0 - 1, x0 - 1, H, W, lane, wave);
+    fused_layer<16>(sA2, H2, W2, sA1, frag + FP_L3 * 64, bias4(FP_B3), y0 - 1, x0 - 1, H, W, lane, wave);
     __syncthreads();
     // Layer 4, step 1: P[t][p] = sum over the 16 channels of W4[c][t] a3[p][c], tap-major in a2's buffer.
     float *P = reinterpret_cast<float *>(sA2);
-    const bf16x4 w4 = __builtin_bit_cast(bf16x4, frag[FP_L4 + lane]);
+    const uint4 f4 = frag[FP_L4 * 64 + lane];
+    const bf16x4 w4 = __builtin_bit_cast(bf16x4, make_uint2(f4.x, f4.y));
     for (int g = wave; g < (N3 + 15) / 16; g += FT_NW) {
         const int p = g * 16 + n;
         const int pc = p < N3 ? p : N3 - 1;
@@ -681,7 +699,7 @@ static LrLayout lr_layout(int B, int H, int W, bool train)
     L.nb4 = nb4;
     L.nbc = nbc;
     size_t o = 0;
-    L.frag = o; o += al(FP_FRAGS * 8);
+    L.frag = o; o += al(FP_FRAGS * 16);
     L.fl = o; o += al(FP_FLOATS * 4);
     if (!train) {  // fused inference keeps activations on chip
         L.total = o;
@@ -763,7 +781,7 @@ int lrnet_forward(const float *params, const float *feat, int B, int H, int W, f
                   uint8_t *ws, hipStream_t st)
 {
     const LrLayout L = lr_layout(B, H, W, false);
-    uint2 *frag = reinterpret_cast<uint2 *>(ws + L.frag);
+    uint4 *frag = reinterpret_cast<uint4 *>(ws + L.frag);
     float *fl = reinterpret_cast<float *>(ws + L.fl);
     ProfScope prof("lrnet_fused", st);
     hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_FRAGS / 64), dim3(64), 0, st, params, frag, fl);
