@@ -503,7 +503,8 @@ typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// Two FP32 values that are not NaN -> packed BF16 (low half = a), round to nearest even.
+// Two FP32 values -> packed BF16 (low half = a), round to nearest even (a NaN
+// stays a NaN).
 __device__ __forceinline__ uint32_t bf16x2_bits(float a, float b)
 {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2v));
@@ -640,9 +641,8 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
         const int gy = y0 + ly - 4, gx = x0 + lx - 4;
         float4 f = make_float4(0.f, 0.f, 0.f, 0.f);
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) f = feat[img + (size_t)gy * W + gx];
-        reinterpret_cast<uint2 *>(sF)[i] =
-            make_uint2((uint32_t)bf16_bits(f.x) | ((uint32_t)bf16_bits(f.y) << 16),
-                       (uint32_t)bf16_bits(f.z) | ((uint32_t)bf16_bits(f.w) << 16));
+        // BF16 rounding (round to nearest even; NaN stays NaN).
+        reinterpret_cast<uint2 *>(sF)[i] = make_uint2(bf16x2_bits(f.x, f.y), bf16x2_bits(f.z, f.w));
     }
     __syncthreads();
     const int n = lane & 15, kg = lane >> 4;
