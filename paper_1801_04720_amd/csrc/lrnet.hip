@@ -492,7 +492,8 @@ __global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *
 // channel) puts its 9 taps on the rows of A: one MFMA per 16 pixels gives the
 // per-tap channel sums P_t(p), which go to LDS, and the logit at p is
 // b4 + sum over taps t of P_t(p + offset_t).  Weight fragments come pre-packed
-// per lane (pack_fused_kernel), 16 bytes per lane and slot.
+// per lane (pack_fused_kernel), 16 bytes per lane and slot; each block copies
+// them to LDS while its features load.
 constexpr int FT_H = 16, FT_W = 32;
 constexpr int FT_NW = 16;  // waves per block: they share the tile's LDS, so more of them hide latency
 constexpr int FP_L1 = 0, FP_L2 = 2, FP_L3 = 7, FP_L4 = 12, FP_NSLOT = 13;  // uint4 slots of 64 lanes
@@ -632,6 +633,7 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
     __shared__ __align__(16) uint16_t sF[FH * FW * 4];
     __shared__ __align__(16) uint16_t sA1[H1 * W1 * 16];
     __shared__ __align__(16) uint16_t sA2[H2 * W2 * 16];
+    __shared__ __align__(16) uint4 sW[FP_FRAGS];  // weight fragments [slot][lane], staged from global
     const int b = blockIdx.z;
     const int x0 = blockIdx.x * FT_W, y0 = blockIdx.y * FT_H;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -644,18 +646,19 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
         // BF16 rounding (round to nearest even; NaN stays NaN).
         reinterpret_cast<uint2 *>(sF)[i] = make_uint2(bf16x2_bits(f.x, f.y), bf16x2_bits(f.z, f.w));
     }
+    for (int i = tid; i < FP_FRAGS; i += 64 * FT_NW) sW[i] = frag[i];
     __syncthreads();
     const int n = lane & 15, kg = lane >> 4;
     auto bias4 = [&](int off) { return f32x4{fl[off + 4 * kg], fl[off + 4 * kg + 1], fl[off + 4 * kg + 2], fl[off + 4 * kg + 3]}; };
-    fused_layer<4>(sF, FH, FW, sA1, frag + FP_L1 * 64, bias4(FP_B1), y0 - 3, x0 - 3, H, W, lane, wave);
+    fused_layer<4>(sF, FH, FW, sA1, sW + FP_L1 * 64, bias4(FP_B1), y0 - 3, x0 - 3, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16>(sA1, H1, W1, sA2, frag + FP_L2 * 64, bias4(FP_B2), y0 - 2, x0 - 2, H, W, lane, wave);
+    fused_layer<16>(sA1, H1, W1, sA2, sW + FP_L2 * 64, bias4(FP_B2), y0 - 2, x0 - 2, H, W, lane, wave);
     __syncthreads();
-    fused_layer<16>(sA2, H2, W2, sA1, frag + FP_L3 * 64, bias4(FP_B3), y0 - 1, x0 - 1, H, W, lane, wave);
+    fused_layer<16>(sA2, H2, W2, sA1, sW + FP_L3 * 64, bias4(FP_B3), y0 - 1, x0 - 1, H, W, lane, wave);
     __syncthreads();
     // Layer 4, step 1: P[t][p] = sum over the 16 channels of W4[c][t] a3[p][c], tap-major in a2's buffer.
     float *P = reinterpret_cast<float *>(sA2);
-    const uint4 f4 = frag[FP_L4 * 64 + lane];
+    const uint4 f4 = sW[FP_L4 * 64 + lane];
     const bf16x4 w4 = __builtin_bit_cast(bf16x4, make_uint2(f4.x, f4.y));
     for (int g = wave; g < (N3 + 15) / 16; g += FT_NW) {
         const int p = g * 16 + n;
