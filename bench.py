@@ -58,18 +58,23 @@ def measured_traffic(kernel):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(fr, D):
+def cpu_baseline(fr, D, runs=3):
+    """The oracle on one stereo pair of the frame, timed `runs` times on one
+    host thread; the median run gives the rate."""
     import oracle
 
-    t = time.perf_counter()
-    oracle.disparity(fr.t0.left, fr.t0.right, D)
-    dt = time.perf_counter() - t
+    times = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        oracle.disparity(fr.t0.left, fr.t0.right, D)
+        times.append(time.perf_counter() - t)
+    dt = sorted(times)[len(times) // 2]
     H, W = fr.t0.left.shape
     return {"value": H * W * D * 8 / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
             "sample": f"one {W}x{H} D={D} stereo pair (t0 of frame 0): census of both views, both "
                       f"cost volumes, both 8-path aggregations, WTA, sub-pixel, LR check; "
-                      f"single thread, {dt:.2f} s",
-            "seconds": dt}
+                      f"single thread, median of {runs} runs ({', '.join(f'{x:.2f}' for x in times)} s)",
+            "seconds": dt, "runs_s": times}
 
 
 def _gen_pair(arg):
