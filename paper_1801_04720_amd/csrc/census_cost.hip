@@ -35,13 +35,20 @@ __global__ __launch_bounds__(CEN_TX *CEN_TH) void census_kernel(CensusArgs a)
     const int x0 = blockIdx.x * CEN_TW, y0 = blockIdx.y * CEN_TH;
     const int tid = ty * CEN_TX + tx;
     // Tile byte i of LDS row r is image byte (clamp(y0 + r - RY), clamp(x0 - RX + i)).
-    const bool interior = x0 >= CEN_RX && x0 + CEN_TW + CEN_RX <= W &&
-                          ((reinterpret_cast<uintptr_t>(img) | (uintptr_t)pitch) & 3) == 0;
+    // Away from the left and right image edges a tile dword is assembled from
+    // the two aligned dwords around its four bytes (any base or pitch
+    // alignment); those reads stay inside the row because the tile starts at
+    // least 7 bytes from either end.
+    const bool interior = x0 >= 2 * CEN_RX && x0 + CEN_TW + 2 * CEN_RX <= W;
     if (interior) {
         for (int i = tid; i < CEN_LH * CEN_LW; i += CEN_TX * CEN_TH) {
             const int r = i / CEN_LW, c = i - r * CEN_LW;
             const int gy = min(max(y0 + r - CEN_RY, 0), H - 1);
-            tile[i] = *reinterpret_cast<const uint32_t *>(img + (size_t)gy * pitch + (x0 - CEN_RX) + 4 * c);
+            const uint8_t *src = img + (size_t)gy * pitch + (x0 - CEN_RX) + 4 * c;
+            const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(src) & 3);
+            const uint32_t *al = reinterpret_cast<const uint32_t *>(src - sh);
+            const uint64_t two = (uint64_t)al[0] | ((uint64_t)al[1] << 32);
+            tile[i] = (uint32_t)(two >> (8 * sh));
         }
     } else {
         uint8_t *tb = reinterpret_cast<uint8_t *>(tile);

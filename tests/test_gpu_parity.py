@@ -34,6 +34,22 @@ def test_census(orc, H, W):
     assert np.array_equal(got, orc.census(img))
 
 
+@pytest.mark.parametrize("H,W,pitch,offset", [(40, 1024, 1024, 0), (17, 900, 903, 1), (9, 1300, 1301, 3),
+                                               (12, 1242, 1250, 2)])
+def test_census_interior_tiles(orc, H, W, pitch, offset):
+    """Images wide enough for tiles away from both edges (dword fill from any base and pitch alignment)."""
+    say("census interior", H, W, pitch, offset)
+    rng = np.random.default_rng(W + offset)
+    buf = rng.integers(0, 256, H * pitch + 8).astype(np.uint8)
+    t = dev(buf)
+    out = torch.empty((H, W), dtype=torch.int64, device=DEV)
+    _lib.check(_lib.lib().sf_census(ct.c_void_p(t.data_ptr() + offset), H, W, pitch,
+                                    ct.c_void_p(out.data_ptr()),
+                                    ct.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    img = np.ascontiguousarray(buf[offset:offset + H * pitch].reshape(H, pitch)[:, :W])
+    assert np.array_equal(host(out, np.uint64), orc.census(img))
+
+
 def test_census_pitch(orc):
     say("census pitch")
     rng = np.random.default_rng(5)
