@@ -208,7 +208,7 @@ def bench_stream(args, dev):
     import numpy as np
     import torch
 
-    from paper_1801_04720_amd import batch
+    from paper_1801_04720_amd import api, batch
     from paper_1801_04720_amd.pipeline import FusedFrame
 
     H, W, D = 1024, 2048, 256
@@ -219,8 +219,9 @@ def bench_stream(args, dev):
     frames = [tuple(a.to(dev) for a in f) for f in host]
     with np.load(args.lrnet, allow_pickle=False) as z:
         prm = torch.from_numpy(z["params"].astype(np.float32)).to(dev)
-    t2, _ = batch.autotune(H, W, D, nviews=2, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
-    t4, _ = batch.autotune(H, W, D, nviews=4, cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    t2, _ = batch.frame_autotune(H, W, D, flags=api.FRAME_LEARNED, cache=cache)
+    t4, _ = batch.frame_autotune(H, W, D, cache=cache)
     learned = FusedFrame(H, W, D, learned_params=prm, tuning=t2, device=dev)
     plain = FusedFrame(H, W, D, tuning=t4, device=dev)
     s = torch.cuda.current_stream()
@@ -359,7 +360,7 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     import numpy as np
     import torch
 
-    from paper_1801_04720_amd import lrnet
+    from paper_1801_04720_amd import api, lrnet
     from paper_1801_04720_amd.pipeline import FusedFrame
 
     trained = os.path.exists(args.lrnet)
@@ -373,8 +374,8 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     if not args.no_autotune:
         from paper_1801_04720_amd import batch
 
-        tuning, _ = batch.autotune(H, W, D, nviews=2,
-                                   cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+        tuning, _ = batch.frame_autotune(H, W, D, flags=api.FRAME_LEARNED,
+                                         cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
     lp = FusedFrame(H, W, D, learned_params=prm_t, tuning=tuning, device=dev)
     for _ in range(args.warmup):
         lp.run(*inputs)
@@ -411,13 +412,11 @@ def variants_leg(args, plain_pipe, inputs, fr, H, W, D, ms_plain, dev):
     from paper_1801_04720_amd.pipeline import FusedFrame
 
     lib = _lib.lib()
-    t2 = t4 = None
-    if not args.no_autotune:
+    tuned = not args.no_autotune
+    if tuned:
         from paper_1801_04720_amd import batch
 
         cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
-        t2, _ = batch.autotune(H, W, D, nviews=2, cache=cache)
-        t4, _ = batch.autotune(H, W, D, nviews=4, cache=cache)
     gt = torch.from_numpy(fr.t0.gt_disp).to(dev)
     plain = plain_pipe.run(*inputs)
     plain = {k: plain[k].clone() for k in ("valid0", "valid1", "disp0", "sf4", "valid")}
@@ -445,7 +444,10 @@ def variants_leg(args, plain_pipe, inputs, fr, H, W, D, ms_plain, dev):
     for name, kw in (("diag", dict(diag=True)), ("median", dict(median=True)),
                      ("adaptive_p2", dict(adaptive_p2=True)),
                      ("diag_median_adaptive", dict(diag=True, median=True, adaptive_p2=True))):
-        fp = FusedFrame(H, W, D, tuning=t2 if kw.get("diag") else t4, device=dev, **kw)
+        flags = ((api.FRAME_DIAG if kw.get("diag") else 0) | (api.FRAME_MEDIAN if kw.get("median") else 0) |
+                 (api.FRAME_ADAPTIVE_P2 if kw.get("adaptive_p2") else 0))
+        tun = batch.frame_autotune(H, W, D, flags=flags, cache=cache)[0] if tuned else None
+        fp = FusedFrame(H, W, D, tuning=tun, device=dev, **kw)
         for _ in range(args.warmup):
             fp.run(*inputs)
         torch.cuda.synchronize()
@@ -684,8 +686,8 @@ def main():
     if args.pipeline != "stages" and not args.no_autotune:
         from paper_1801_04720_amd import batch
 
-        tuning, t_ms = batch.autotune(H, W, D, nviews=4,
-                                      cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+        tuning, t_ms = batch.frame_autotune(H, W, D,
+                                            cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
         tuning_info = dict(batch.tuning_dict(tuning), tuner_ms=t_ms)
     if args.pipeline == "stages":
         pipe = PlainFrame(H, W, D, device=dev)
@@ -695,7 +697,11 @@ def main():
         pipe.run(L0, R0, L1, R1, flow)
     torch.cuda.synchronize()
 
+    # Dominant kernel: the path aggregation (one launch for all 4 views, or one per view).
+    kname, views_per_launch = ("sgm_paths", 1) if args.pipeline == "stages" else ("sgm_tasks", 4)
+    # Timed region: HIP events on the launch stream around the dominant kernel only.
     _lib.check(lib.sf_prof_enable(64 * max(args.steps, 1)))
+    _lib.check(lib.sf_prof_only(kname.encode()))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -703,30 +709,34 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     lib.sf_prof_disable()
+    dom_tot, dom_n = kernel_ms(lib, kname)
+    lib.sf_prof_only(None)
 
     ms = 1e3 * elapsed / max(args.steps, 1)
     cells = H * W * D * 8
     gcups_delivered = 2 * cells / (ms * 1e-3) / 1e9
     gcups_passes = 4 * cells / (ms * 1e-3) / 1e9
+    # Per-kernel breakdown from a separate pass with every launch timed (outside the timed region).
+    nb = max(min(args.steps, 20), 1)
+    _lib.check(lib.sf_prof_enable(64 * nb))
+    for _ in range(nb):
+        pipe.run(L0, R0, L1, R1, flow)
+    torch.cuda.synchronize()
+    lib.sf_prof_disable()
     breakdown = {}
     for name in ["census", "cost", "sgm_paths", "sgm_tasks", "slab_sum", "wta_right", "wta_left",
                  "wta_slab_right", "wta_slab_left", "combine"]:
         tot, n = kernel_ms(lib, name)
         if n:
-            breakdown[name] = {"avg_ms": tot / n, "launches": n, "ms_per_frame": tot / args.steps}
-    # Dominant kernel: the path aggregation (one launch per view, or one for all 4 views).
-    if "sgm_tasks" in breakdown:
-        kname, views_per_launch = "sgm_tasks", 4
-    else:
-        kname, views_per_launch = "sgm_paths", 1
-    sg = breakdown[kname]
+            breakdown[name] = {"avg_ms": tot / n, "launches": n, "ms_per_frame": tot / nb}
+    sg = {"avg_ms": dom_tot / max(dom_n, 1), "launches": dom_n}
     avg_s = sg["avg_ms"] * 1e-3
     ops = 8 * cells * views_per_launch  # u16 element ops: 8 per cell update
     achieved = ops / avg_s / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": PEAK_U16_TOPS, "unit": "TOP/s (packed u16)",
                 "frac": achieved / PEAK_U16_TOPS, "traffic": measured_traffic(kname),
-                "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"],
+                "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"], "timed_launches": sg["launches"],
                 "gcups_per_launch": cells * views_per_launch / avg_s / 1e9}
     if roofline["traffic"]:
         # The launch's HBM-side bytes per second against the 8 TB/s HBM peak: the

@@ -245,6 +245,18 @@ int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8
                  uint8_t *valid, float *xyz0, float *motion, void *workspace, size_t ws_bytes,
                  void *stream);
 
+/* Frame autotuner: times whole frames (sf_frame_run, or sf_frame_run_learned
+ * with zero network parameters) of a plan with the given size, penalties and
+ * flags for every candidate aggregation tuning (chains per block x prefetch x
+ * order x persistence), on seeded synthetic images, and returns the tuning with
+ * the fastest median frame and that time in ms.  In a frame the aggregation
+ * shares the memory system with the cost and WTA stages, so this choice can
+ * differ from sf_agg_autotune's.  Allocates and frees its own buffers;
+ * synchronises the stream.  Errors: those of sf_frame_plan_create, SF_EINVAL
+ * (NULL best), SF_EHIP. */
+int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol, int flags, void *stream,
+                      sf_agg_tuning *best, float *best_ms);
+
 /* Learned frame (plan created with SF_FRAME_LEARNED): as sf_frame_run, except
  * that only the two left-base views are aggregated, WTA also writes the
  * network's features, and each map's validity is sf_lrnet_mask of
@@ -290,8 +302,10 @@ int sf_batch_launch(sf_plan plan, void *stream);
 /* Autotuner: times every candidate tuning (chains per block x prefetch x order x
  * persistence) of one aggregation launch over nviews views of H x W x D
  * (synthetic costs; 2 = a stereo pair, 4 = a scene-flow frame) on `stream`, and
- * returns the fastest and its median time.  Allocates and frees its own
- * scratch; synchronises the stream. */
+ * returns the fastest and its median time over five runs, each started right
+ * after the cost volumes were rewritten (as in a frame, where the cost stage
+ * precedes the aggregation).  Allocates and frees its own scratch;
+ * synchronises the stream. */
 int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, void *stream,
                     sf_agg_tuning *best, float *best_ms);
 
@@ -336,8 +350,11 @@ int sf_lrnet_adam(float *params, float *m, float *v, const float *grad, int n, f
  * of HIP events on its own stream; sf_prof_query waits for and sums those of one
  * kernel name.  At most max_launches launches are recorded per enable.  The
  * events are created by sf_prof_enable (call it outside any timed region).
+ * sf_prof_only(name) restricts the recording to launches of that name (NULL:
+ * all), so that a timed region carries the events of one kernel only.
  * Process-wide, single-threaded use.  Errors: SF_EINVAL, SF_EHIP. */
 int sf_prof_enable(int max_launches);
+int sf_prof_only(const char *kernel);
 int sf_prof_disable(void);
 int sf_prof_query(const char *kernel, double *total_ms, int *launches);
 

@@ -74,7 +74,9 @@ SIGNATURES = {
     "sf_batch_capture": (I, [P, P, SZ, P]),
     "sf_batch_launch": (I, [P, P]),
     "sf_agg_autotune": (I, [I, I, I, I, I, I, P, ct.POINTER(SfAggTuning), ct.POINTER(F)]),
+    "sf_frame_autotune": (I, [I, I, I, I, I, I, I, P, ct.POINTER(SfAggTuning), ct.POINTER(F)]),
     "sf_prof_enable": (I, [I]),
+    "sf_prof_only": (I, [ct.c_char_p]),
     "sf_prof_disable": (I, []),
     "sf_prof_query": (I, [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(I)]),
     "sf_sgm_aggregate_adaptive": (I, [P, P, I, I, I, I, I, I, U32, P, P, SZ, P]),

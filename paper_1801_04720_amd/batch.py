@@ -55,6 +55,32 @@ def autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, cache: str | N
     return best, float(ms.value)
 
 
+def frame_autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: int = 1, flags: int = 0,
+                   cache: str | None = DEFAULT_CACHE, stream=None,
+                   refresh: bool = False) -> tuple[SfAggTuning, float | None]:
+    """Aggregation tuning with the fastest whole frame (sf_frame_autotune) for a
+    frame plan of this size, penalties and flags, cached per arch and key."""
+    key = f"{_arch()}:frame:{H}x{W}x{D}:P1={P1}:P2={P2}:tol={lr_tol}:flags={flags}"
+    db = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            db = json.load(f)
+    if key in db and not refresh:
+        e = db[key]
+        return SfAggTuning(e["chains_per_block"], e["prefetch"], e["order"], e["persistent_per_cu"]), e.get("ms")
+    best = SfAggTuning()
+    ms = ct.c_float(0.0)
+    check(lib().sf_frame_autotune(H, W, D, P1, P2, lr_tol, flags, _stream(stream), ct.byref(best), ct.byref(ms)))
+    if cache:
+        db[key] = dict(tuning_dict(best), ms=float(ms.value))
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        tmp = cache + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return best, float(ms.value)
+
+
 class Batch:
     """A batch of stereo pairs (dicts with uint8 'left', 'right' tensors on the GPU
     and 'D'); outputs per pair: wta int16, disp float32, valid uint8."""

@@ -26,6 +26,7 @@ struct ProfRec {
     hipEvent_t start, stop;
 };
 static bool g_prof_on = false;
+static std::string g_prof_only;  // record only launches of this name (empty = all)
 static std::vector<hipEvent_t> g_prof_pool;
 static size_t g_prof_next = 0;
 static std::vector<ProfRec> g_prof_recs;
@@ -33,6 +34,7 @@ static std::vector<ProfRec> g_prof_recs;
 ProfScope::ProfScope(const char *name, hipStream_t st) : st_(st), idx_(-1)
 {
     if (!g_prof_on || g_prof_next + 2 > g_prof_pool.size()) return;
+    if (!g_prof_only.empty() && g_prof_only != name) return;
     ProfRec r{name, g_prof_pool[g_prof_next], g_prof_pool[g_prof_next + 1]};
     g_prof_next += 2;
     hipEventRecord(r.start, st);
@@ -60,6 +62,13 @@ extern "C" int sf_prof_enable(int max_launches)
     g_prof_next = 0;
     g_prof_recs.clear();
     g_prof_on = true;
+    return SF_OK;
+}
+
+extern "C" int sf_prof_only(const char *kernel)
+{
+    sf::clear_error();
+    sf::g_prof_only = kernel ? kernel : "";
     return SF_OK;
 }
 

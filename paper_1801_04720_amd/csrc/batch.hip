@@ -450,8 +450,13 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
                                                 st, cpb, pf);
                     };
                     if ((rc = go())) break;
-                    float tms[3];
-                    for (int rep = 0; rep < 3 && rc == SF_OK; ++rep) {
+                    float tms[5];
+                    for (int rep = 0; rep < 5 && rc == SF_OK; ++rep) {
+                        // As in a frame, the cost volumes have just been written
+                        // when the aggregation starts (they may sit in the last-level cache).
+                        for (int v = 0; v < nviews; ++v)
+                            hipLaunchKernelGGL(fill_random_cost_kernel, dim3(4096), dim3(256), 0, st,
+                                               ws + v * vbytes, ncell, 1234u + v);
                         hipEventRecord(e0, st);
                         rc = go();
                         hipEventRecord(e1, st);
@@ -459,9 +464,9 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
                         hipEventElapsedTime(&tms[rep], e0, e1);
                     }
                     if (rc) break;
-                    std::sort(tms, tms + 3);
-                    if (tms[1] < best_t) {
-                        best_t = tms[1];
+                    std::sort(tms, tms + 5);
+                    if (tms[2] < best_t) {
+                        best_t = tms[2];
                         *best = sf_agg_tuning{cpb, pf, order, pp};
                     }
                 }

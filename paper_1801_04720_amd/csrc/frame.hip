@@ -8,8 +8,10 @@
 // aggregation over all 4 views (u8 slabs), WTA of both right views, WTA +
 // sub-pixel + LR check of both left views (slabs summed on the fly, S never
 // written), and the combination.
+#include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "sf_internal.hpp"
 #include "sgm_tasks.hpp"
@@ -373,4 +375,113 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
         if (p->median && (rc = launch_median_mask(dsub, vld[t], H, W, dsp[t], st))) return rc;
     }
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
+}
+
+// --- frame autotuner ----------------------------------------------------------
+namespace {
+// Seeded bytes (hash of the word index) or zeros, for the autotuner's inputs.
+__global__ void tune_fill_kernel(uint32_t *p, size_t nwords, uint32_t seed, int random)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t h = 0;
+        if (random) {
+            h = (uint32_t)i * 0x9E3779B1u ^ seed;
+            h ^= h >> 15;
+            h *= 0x2C1B3C6Du;
+            h ^= h >> 12;
+        }
+        p[i] = h;
+    }
+}
+
+size_t al256f(size_t v) { return (v + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol, int flags,
+                                 void *stream, sf_agg_tuning *best, float *best_ms)
+{
+    clear_error();
+    SF_REQUIRE(best, SF_EINVAL, "sf_frame_autotune: NULL best");
+    sf_plan probe = nullptr;
+    int rc = sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, nullptr, &probe);
+    if (rc) return rc;
+    const size_t ws_bytes = sf_plan_workspace_bytes(probe);
+    sf_plan_destroy(probe);
+    const bool learned = (flags & SF_FRAME_LEARNED) != 0;
+    hipStream_t st = as_stream(stream);
+    // One allocation: 4 images, flow, network parameters, the outputs, the workspace.
+    const size_t npx = (size_t)H * W;
+    size_t off = 0;
+    const size_t o_img = off; off += al256f(4 * npx);
+    const size_t o_flow = off; off += al256f(npx * 8);
+    const size_t o_prm = off; off += al256f((size_t)sf_lrnet_nparams() * 4);
+    const size_t o_d0 = off; off += al256f(npx * 4);
+    const size_t o_v0 = off; off += al256f(npx);
+    const size_t o_d1 = off; off += al256f(npx * 4);
+    const size_t o_v1 = off; off += al256f(npx);
+    const size_t o_sf = off; off += al256f(npx * 16);
+    const size_t o_v = off; off += al256f(npx);
+    const size_t o_xyz = off; off += al256f(npx * 12);
+    const size_t o_mot = off; off += al256f(npx * 12);
+    const size_t o_ws = off; off += al256f(ws_bytes);
+    uint8_t *buf = nullptr;
+    if (hipMalloc(&buf, off) != hipSuccess) return fail(SF_EHIP, "sf_frame_autotune: hipMalloc");
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(2048), dim3(256), 0, st, reinterpret_cast<uint32_t *>(buf),
+                       o_ws / 4, 0x5EEDu, 0);
+    hipLaunchKernelGGL(tune_fill_kernel, dim3(2048), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t *>(buf + o_img), (4 * npx) / 4, 0x5EEDu, 1);
+    const uint8_t *img[4];
+    for (int i = 0; i < 4; ++i) img[i] = buf + o_img + i * npx;
+    const sf_camera cam{721.5f, 0.54f, 0.5f * (float)(W - 1), 0.5f * (float)(H - 1)};
+    auto run = [&](sf_plan pl) {
+        float *d0 = reinterpret_cast<float *>(buf + o_d0), *d1 = reinterpret_cast<float *>(buf + o_d1);
+        float *sf = reinterpret_cast<float *>(buf + o_sf), *xyz = reinterpret_cast<float *>(buf + o_xyz);
+        float *mot = reinterpret_cast<float *>(buf + o_mot);
+        const float *flow = reinterpret_cast<const float *>(buf + o_flow);
+        if (learned)
+            return sf_frame_run_learned(pl, img[0], img[1], img[2], img[3], W, flow, &cam,
+                                        reinterpret_cast<const float *>(buf + o_prm), d0, buf + o_v0, d1,
+                                        buf + o_v1, sf, buf + o_v, xyz, mot, buf + o_ws, ws_bytes, stream);
+        return sf_frame_run(pl, img[0], img[1], img[2], img[3], W, flow, &cam, d0, buf + o_v0, d1,
+                            buf + o_v1, sf, buf + o_v, xyz, mot, buf + o_ws, ws_bytes, stream);
+    };
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best_t = 1e30f;
+    // Candidates: chains per block x order x prefetch x persistent blocks per CU.
+    std::vector<sf_agg_tuning> cand;
+    for (int cpb : {4, 8, 16})
+        for (int order : {0, 1})
+            for (int pf : {4, 8})
+                for (int pp : {0, 4, 8}) cand.push_back(sf_agg_tuning{cpb, pf, order, pp});
+    constexpr int REPS = 5, FRAMES = 3;
+    for (size_t c = 0; c < cand.size() && rc == SF_OK; ++c) {
+        sf_plan pl = nullptr;
+        if ((rc = sf_frame_plan_create(H, W, D, P1, P2, lr_tol, flags, &cand[c], &pl))) break;
+        for (int w = 0; w < 2 && rc == SF_OK; ++w) rc = run(pl);
+        float tms[REPS];
+        for (int r = 0; r < REPS && rc == SF_OK; ++r) {
+            hipEventRecord(e0, st);
+            for (int f = 0; f < FRAMES && rc == SF_OK; ++f) rc = run(pl);
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            hipEventElapsedTime(&tms[r], e0, e1);
+            tms[r] /= FRAMES;
+        }
+        sf_plan_destroy(pl);
+        if (rc) break;
+        std::sort(tms, tms + REPS);
+        if (tms[REPS / 2] < best_t) {
+            best_t = tms[REPS / 2];
+            *best = cand[c];
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(buf);
+    if (rc) return rc;
+    if (best_ms) *best_ms = best_t;
+    return SF_OK;
 }

@@ -586,7 +586,6 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
     if (chains_per_block != 4 && chains_per_block != 8 && chains_per_block != 16)
         return fail(SF_EINVAL, "launch_agg_tasks: chains per block must be 4, 8 or 16");
     if (prefetch != 4 && prefetch != 8) return fail(SF_EINVAL, "launch_agg_tasks: prefetch must be 4 or 8");
-    ProfScope prof("sgm_tasks", st);
     int nb = ntasks;
     int *counter = nullptr;
     if (persistent_blocks > 0) {
@@ -595,6 +594,7 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
         nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
         counter = d_counter;
     }
+    ProfScope prof("sgm_tasks", st);  // the aggregation launch alone
     const int nthr = 16 * chains_per_block;
     switch (K) {
     case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;

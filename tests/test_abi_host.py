@@ -133,3 +133,12 @@ def test_volume_offset_limit(L):
     pair = _lib.SfPair(8192, 1024, 256, 1024, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
     arr = (_lib.SfPair * 1)(pair)
     expect(L.sf_batch_plan_create(arr, 1, 10, 120, 1, None, 0, 0, ct.byref(plan)), 1, "2^31")
+
+
+def test_frame_autotune_validation(L):
+    t = _lib.SfAggTuning()
+    ms = ct.c_float()
+    expect(L.sf_frame_autotune(64, 64, 32, 10, 120, 1, 0, None, None, ct.byref(ms)), 1, "NULL best")
+    # Invalid plans are refused before any buffer is allocated.
+    expect(L.sf_frame_autotune(64, 64, 32, 10, 120, 1, 4 | 2, None, ct.byref(t), ct.byref(ms)), 1, "exclude")
+    expect(L.sf_frame_autotune(8192, 1024, 256, 10, 120, 1, 0, None, ct.byref(t), ct.byref(ms)), 1, "2^31")

@@ -120,3 +120,26 @@ def test_autotune_returns_valid_choice(tmp_path):
     t2, ms2 = batch.autotune(96, 320, 32, cache=str(tmp_path / "at.json"))
     assert (t2.chains_per_block, t2.prefetch, t2.order, t2.persistent_per_cu) == \
         (t.chains_per_block, t.prefetch, t.order, t.persistent_per_cu)
+
+
+def test_frame_autotune_returns_valid_choice(tmp_path):
+    """Whole-frame tuner: a valid candidate, cached, and a frame with it equals the default plan's."""
+    from paper_1801_04720_amd.pipeline import FusedFrame
+
+    say("frame autotune")
+    H, W, D = 48, 160, 32
+    t, ms = batch.frame_autotune(H, W, D, cache=str(tmp_path / "ft.json"))
+    assert t.chains_per_block in (4, 8, 16) and t.prefetch in (4, 8)
+    assert t.order in (0, 1) and t.persistent_per_cu in (0, 4, 8)
+    assert ms > 0
+    t2, _ = batch.frame_autotune(H, W, D, cache=str(tmp_path / "ft.json"))
+    assert (t2.chains_per_block, t2.prefetch, t2.order, t2.persistent_per_cu) == \
+        (t.chains_per_block, t.prefetch, t.order, t.persistent_per_cu)
+    fr = synth.frame_planar(synth.rng_for(8, 31), H, W, D, 10.0)
+    args = [dev(a) for a in (fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right, fr.flow)]
+    a = FusedFrame(H, W, D, device=DEV).run(*args)
+    b = FusedFrame(H, W, D, tuning=t, device=DEV).run(*args)
+    torch.cuda.synchronize()
+    for k in ("disp0", "valid0", "disp1", "valid1", "valid"):
+        assert np.array_equal(host(a[k]), host(b[k])), k
+    assert np.array_equal(host(a["sf4"]), host(b["sf4"]), equal_nan=True)
