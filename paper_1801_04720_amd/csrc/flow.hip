@@ -31,9 +31,16 @@ namespace sf {
 constexpr int FL_T = 16;
 constexpr int FL_MAXLEV = 16;
 
-__global__ __launch_bounds__(256) void pyr_down_kernel(const uint8_t *__restrict__ in, int H, int W,
-                                                       int pitch, uint8_t *__restrict__ out)
+// Two images per launch (blockIdx.y selects the image).
+struct PyrArgs {
+    const uint8_t *in[2];
+    uint8_t *out[2];
+};
+
+__global__ __launch_bounds__(256) void pyr_down_kernel(PyrArgs a, int H, int W, int pitch)
 {
+    const uint8_t *__restrict__ in = a.in[blockIdx.y];
+    uint8_t *__restrict__ out = a.out[blockIdx.y];
     const int w = (W + 1) / 2, h = (H + 1) / 2;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= w * h) return;
@@ -70,13 +77,24 @@ __device__ __forceinline__ int flow_cost(const uint64_t (&a)[9], const uint64_t 
     return s;
 }
 
-__global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__restrict__ c0,
-                                                             const uint64_t *__restrict__ c1, int H,
-                                                             int W, int level, int iter, int Rl,
-                                                             uint64_t seed,
-                                                             const short2 *__restrict__ fin,
-                                                             short2 *__restrict__ fout)
+// One iteration of both flow directions (blockIdx.z = direction d: the flow
+// from image d to image 1 - d, with its own seed and flow buffers).
+struct PmArgs {
+    const uint64_t *c0[2], *c1[2];  // census of the source and target image
+    const short2 *fin[2];
+    short2 *fout[2];
+    uint64_t seed[2];
+};
+
+__global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(PmArgs pa, int H, int W, int level,
+                                                             int iter, int Rl)
 {
+    const int dz = blockIdx.z;
+    const uint64_t *__restrict__ c0 = pa.c0[dz];
+    const uint64_t *__restrict__ c1 = pa.c1[dz];
+    const short2 *__restrict__ fin = pa.fin[dz];
+    short2 *__restrict__ fout = pa.fout[dz];
+    const uint64_t seed = pa.seed[dz];
     const int x = blockIdx.x * FL_T + threadIdx.x, y = blockIdx.y * FL_T + threadIdx.y;
     if (x >= W || y >= H) return;
     uint64_t a[9];
@@ -137,9 +155,16 @@ __global__ __launch_bounds__(FL_T *FL_T) void pm_iter_kernel(const uint64_t *__r
 
 // Start of a level: zero on the coarsest, else twice the coarser flow at
 // (x/2, y/2) with the target clamped into the image.
-__global__ __launch_bounds__(256) void flow_init_kernel(const short2 *__restrict__ coarse, int hc,
-                                                        int wc, int H, int W, short2 *__restrict__ out)
+// Both directions per launch (blockIdx.y = direction).
+struct InitArgs {
+    const short2 *coarse[2];  // NULL on the coarsest level
+    short2 *out[2];
+};
+
+__global__ __launch_bounds__(256) void flow_init_kernel(InitArgs a, int hc, int wc, int H, int W)
 {
+    const short2 *__restrict__ coarse = a.coarse[blockIdx.y];
+    short2 *__restrict__ out = a.out[blockIdx.y];
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= H * W) return;
     const int y = i / W, x = i - y * W;
@@ -150,13 +175,6 @@ __global__ __launch_bounds__(256) void flow_init_kernel(const short2 *__restrict
     const short2 c = coarse[(size_t)min(y / 2, hc - 1) * wc + min(x / 2, wc - 1)];
     const int fu = 2 * c.x, fv = 2 * c.y;
     out[i] = make_short2((short)(min(max(x + fu, 0), W - 1) - x), (short)(min(max(y + fv, 0), H - 1) - y));
-}
-
-__global__ __launch_bounds__(256) void copy_flow_kernel(const short2 *__restrict__ in, int n,
-                                                        short2 *__restrict__ out)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) out[i] = in[i];
 }
 
 __global__ __launch_bounds__(256) void fb_check_kernel(const short2 *__restrict__ F,
@@ -183,7 +201,7 @@ struct FlowLayout {
     int h[FL_MAXLEV], w[FL_MAXLEV];
     size_t off_img[2][FL_MAXLEV];  // level >= 1 images of A and B
     size_t off_cen[2][FL_MAXLEV];  // census of A and B per level
-    size_t off_f[2];               // ping-pong flow buffers (full size)
+    size_t off_f[2][2];            // ping-pong flow buffers per direction (full size)
     size_t bytes;
 };
 
@@ -210,41 +228,55 @@ static FlowLayout flow_layout(int H, int W, int levels)
             L.off_cen[s][l] = off;
             off += al256(n * 8);
         }
-    for (int k = 0; k < 2; ++k) {
-        L.off_f[k] = off;
-        off += al256((size_t)H * W * 4);
-    }
+    for (int d = 0; d < 2; ++d)
+        for (int k = 0; k < 2; ++k) {
+            L.off_f[d][k] = off;
+            off += al256((size_t)H * W * 4);
+        }
     L.bytes = off;
     return L;
 }
 
-// Integer flow from image s to image 1-s over the prepared pyramid / census.
-static int run_direction(const FlowLayout &L, uint8_t *ws, int s, int iters, int R, int fine_radius,
-                         uint64_t seed, short2 *result, hipStream_t st)
+// Integer flows from image 0 to image 1 (F) and from image 1 to image 0 (B)
+// over the prepared pyramid / census, both directions in every launch; the last
+// iteration of the finest level writes F and B.
+static int run_directions(const FlowLayout &L, uint8_t *ws, int iters, int R, int fine_radius,
+                          const uint64_t seed[2], short2 *F, short2 *B, hipStream_t st)
 {
-    short2 *buf[2] = {reinterpret_cast<short2 *>(ws + L.off_f[0]), reinterpret_cast<short2 *>(ws + L.off_f[1])};
-    int cur = 0;
+    short2 *buf[2][2];
+    for (int d = 0; d < 2; ++d)
+        for (int k = 0; k < 2; ++k) buf[d][k] = reinterpret_cast<short2 *>(ws + L.off_f[d][k]);
+    short2 *result[2] = {F, B};
+    int cur = 0;  // both directions keep their current field in buf[d][cur]
     for (int l = L.levels - 1; l >= 0; --l) {
         const int h = L.h[l], w = L.w[l], n = h * w;
-        const short2 *coarse = l == L.levels - 1 ? nullptr : buf[cur];
-        const int dst = l == L.levels - 1 ? cur : 1 - cur;
-        hipLaunchKernelGGL(flow_init_kernel, dim3((n + 255) / 256), dim3(256), 0, st, coarse,
-                           l + 1 < L.levels ? L.h[l + 1] : 1, l + 1 < L.levels ? L.w[l + 1] : 1, h, w,
-                           buf[dst]);
+        const bool coarsest = l == L.levels - 1;
+        const int dst = coarsest ? cur : 1 - cur;
+        InitArgs ia{};
+        for (int d = 0; d < 2; ++d) {
+            ia.coarse[d] = coarsest ? nullptr : buf[d][cur];
+            ia.out[d] = buf[d][dst];
+        }
+        hipLaunchKernelGGL(flow_init_kernel, dim3((n + 255) / 256, 2), dim3(256), 0, st, ia,
+                           coarsest ? 1 : L.h[l + 1], coarsest ? 1 : L.w[l + 1], h, w);
         cur = dst;
-        const uint64_t *c0 = reinterpret_cast<const uint64_t *>(ws + L.off_cen[s][l]);
-        const uint64_t *c1 = reinterpret_cast<const uint64_t *>(ws + L.off_cen[1 - s][l]);
-        dim3 grid((w + FL_T - 1) / FL_T, (h + FL_T - 1) / FL_T);
+        dim3 grid((w + FL_T - 1) / FL_T, (h + FL_T - 1) / FL_T, 2);
         int Rl = max(1, R >> l);
         if (l < L.levels - 1 && fine_radius > 0 && Rl > fine_radius) Rl = fine_radius;
         for (int it = 0; it < iters; ++it) {
-            hipLaunchKernelGGL(pm_iter_kernel, grid, dim3(FL_T, FL_T), 0, st, c0, c1, h, w, l, it, Rl, seed,
-                               buf[cur], buf[1 - cur]);
+            const bool last = l == 0 && it == iters - 1;
+            PmArgs pa{};
+            for (int d = 0; d < 2; ++d) {
+                pa.c0[d] = reinterpret_cast<const uint64_t *>(ws + L.off_cen[d][l]);
+                pa.c1[d] = reinterpret_cast<const uint64_t *>(ws + L.off_cen[1 - d][l]);
+                pa.fin[d] = buf[d][cur];
+                pa.fout[d] = last ? result[d] : buf[d][1 - cur];
+                pa.seed[d] = seed[d];
+            }
+            hipLaunchKernelGGL(pm_iter_kernel, grid, dim3(FL_T, FL_T), 0, st, pa, h, w, l, it, Rl);
             cur = 1 - cur;
         }
     }
-    const int n = L.h[0] * L.w[0];
-    hipLaunchKernelGGL(copy_flow_kernel, dim3((n + 255) / 256), dim3(256), 0, st, buf[cur], n, result);
     return launch_status("pm_iter_kernel");
 }
 
@@ -282,14 +314,16 @@ extern "C" int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, i
     ProfScope prof("flow", st);
     // Pyramids of both images, then the census of every level (both images per launch).
     const uint8_t *src[2] = {L0, L1};
-    for (int s = 0; s < 2; ++s)
-        for (int l = 1; l < levels; ++l) {
-            const uint8_t *in = l == 1 ? src[s] : ws + L.off_img[s][l - 1];
-            const int ip = l == 1 ? pitch : L.w[l - 1];
-            const int n = L.h[l] * L.w[l];
-            hipLaunchKernelGGL(pyr_down_kernel, dim3((n + 255) / 256), dim3(256), 0, st, in, L.h[l - 1],
-                               L.w[l - 1], ip, ws + L.off_img[s][l]);
+    for (int l = 1; l < levels; ++l) {
+        PyrArgs pa{};
+        for (int s = 0; s < 2; ++s) {
+            pa.in[s] = l == 1 ? src[s] : ws + L.off_img[s][l - 1];
+            pa.out[s] = ws + L.off_img[s][l];
         }
+        const int n = L.h[l] * L.w[l];
+        hipLaunchKernelGGL(pyr_down_kernel, dim3((n + 255) / 256, 2), dim3(256), 0, st, pa, L.h[l - 1],
+                           L.w[l - 1], l == 1 ? pitch : L.w[l - 1]);
+    }
     int rc = launch_status("pyr_down_kernel");
     if (rc) return rc;
     for (int l = 0; l < levels; ++l) {
@@ -304,10 +338,9 @@ extern "C" int sf_flow(const uint8_t *L0, const uint8_t *L1, int pitch, int H, i
         ca.W = L.w[l];
         if ((rc = launch_census(ca, st))) return rc;
     }
-    if ((rc = run_direction(L, ws, 0, iters, R, fine_radius, seed, reinterpret_cast<short2 *>(F), st)))
-        return rc;
-    if ((rc = run_direction(L, ws, 1, iters, R, fine_radius, seed ^ 0x5bd1e995ULL,
-                            reinterpret_cast<short2 *>(B), st)))
+    const uint64_t seeds[2] = {seed, seed ^ 0x5bd1e995ULL};
+    if ((rc = run_directions(L, ws, iters, R, fine_radius, seeds, reinterpret_cast<short2 *>(F),
+                             reinterpret_cast<short2 *>(B), st)))
         return rc;
     const int n = H * W;
     hipLaunchKernelGGL(fb_check_kernel, dim3((n + 255) / 256), dim3(256), 0, st,
