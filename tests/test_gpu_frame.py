@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from paper_1801_04720_amd import synth  # noqa: E402
+from paper_1801_04720_amd import _lib, synth  # noqa: E402
 from paper_1801_04720_amd.pipeline import FusedFrame, PlainFrame  # noqa: E402
 
 from gpu_util import DEV, assert_close_rel, dev, host  # noqa: E402
@@ -209,3 +209,40 @@ def test_learned_frame_network_vs_oracle_1242x375(orc):
     assert np.quantile(err, 0.999) <= 0.05 * (1 + np.abs(ref)).max()
     far = np.abs(ref) > 0.05
     assert np.array_equal(logits[far] > 0, ref[far] > 0)
+
+
+def test_kernel_timer_filter():
+    """sf_prof_only: while a name is set, only that kernel's launches are timed."""
+    import ctypes as ct
+
+    say("kernel timer filter")
+    lib = _lib.lib()
+    H, W, D = 40, 96, 32
+    fr = synth.frame_planar(synth.rng_for(8, 41), H, W, D, 10.0)
+    args = [dev(a) for a in (fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right, fr.flow)]
+    ff = FusedFrame(H, W, D, device=DEV)
+
+    def count(name):
+        tot, n = ct.c_double(0.0), ct.c_int(0)
+        _lib.check(lib.sf_prof_query(name.encode(), ct.byref(tot), ct.byref(n)))
+        return n.value, tot.value
+
+    try:
+        _lib.check(lib.sf_prof_enable(256))
+        _lib.check(lib.sf_prof_only(b"sgm_tasks"))
+        for _ in range(3):
+            ff.run(*args)
+        torch.cuda.synchronize()
+        lib.sf_prof_disable()
+        n_agg, t_agg = count("sgm_tasks")
+        assert n_agg == 3 and t_agg > 0
+        assert count("census")[0] == 0 and count("wta_slab_left")[0] == 0
+        _lib.check(lib.sf_prof_only(None))
+        _lib.check(lib.sf_prof_enable(256))
+        ff.run(*args)
+        torch.cuda.synchronize()
+        lib.sf_prof_disable()
+        assert count("sgm_tasks")[0] == 1 and count("census")[0] == 1
+    finally:
+        lib.sf_prof_disable()
+        lib.sf_prof_only(None)
