@@ -115,17 +115,14 @@ __device__ __forceinline__ int slab_pos_to_d(int pos)
     return q * K + (e >> 1) + (e & 1) * (K >> 1);
 }
 
-// Packed u16 sums of the first ns slabs at pixel px for lane j of a 16-lane
-// group (byte positions [8c, 8c + 8), c = j and j + 16), and the disparity of
-// each position.  All slab loads of the lane are issued before any is used
-// (slabs past ns re-read the last one and are masked to zero), so a wave keeps
-// up to 16 loads in flight.
+// The slab bytes of pixel px that lane j of a 16-lane group sums (positions
+// [8c, 8c + 8), c = j and j + 16): all loads issued at once (slabs past ns
+// re-read the last one; slab_add masks them to zero).
 template <int K>
-__device__ __forceinline__ void slab_sums(const uint8_t *__restrict__ slab, size_t cells, int px,
-                                          int j, int ns, uint32_t (&sv)[2][4], int (&dd)[2][8])
+__device__ __forceinline__ void slab_load(const uint8_t *__restrict__ slab, size_t cells, int px, int j,
+                                          int ns, u32x2 (&w)[2][8])
 {
     constexpr int D = 16 * K;
-    u32x2 w[2][8];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
@@ -137,6 +134,15 @@ __device__ __forceinline__ void slab_sums(const uint8_t *__restrict__ slab, size
                     reinterpret_cast<const u32x2 *>(src + (size_t)min(k, ns - 1) * cells));
         }
     }
+}
+
+// Packed u16 sums of the first ns slabs from slab_load's bytes, and the
+// disparity of each position.
+template <int K>
+__device__ __forceinline__ void slab_add(const u32x2 (&w)[2][8], int j, int ns, uint32_t (&sv)[2][4],
+                                         int (&dd)[2][8])
+{
+    constexpr int D = 16 * K;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int c = j + 16 * i;
@@ -156,6 +162,20 @@ __device__ __forceinline__ void slab_sums(const uint8_t *__restrict__ slab, size
             }
         }
     }
+}
+
+// Packed u16 sums of the first ns slabs at pixel px for lane j of a 16-lane
+// group (byte positions [8c, 8c + 8), c = j and j + 16), and the disparity of
+// each position.  All slab loads of the lane are issued before any is used
+// (slabs past ns re-read the last one and are masked to zero), so a wave keeps
+// up to 16 loads in flight.
+template <int K>
+__device__ __forceinline__ void slab_sums(const uint8_t *__restrict__ slab, size_t cells, int px,
+                                          int j, int ns, uint32_t (&sv)[2][4], int (&dd)[2][8])
+{
+    u32x2 w[2][8];
+    slab_load<K>(slab, cells, px, j, ns, w);
+    slab_add<K>(w, j, ns, sv, dd);
 }
 
 __device__ __forceinline__ uint32_t sv_val(const uint32_t (&sv)[2][4], int i, int e)
@@ -206,20 +226,18 @@ __device__ __forceinline__ float subpixel(int ds, int D, uint32_t av, uint32_t s
     return sub;
 }
 
+// Each 16-lane group takes WTA_G pixels WTA_PPB apart; the slabs of the next
+// pixel are loaded while the current one is reduced, so the loads of a wave
+// stay in flight across its arithmetic.
+constexpr int WTA_G = 4;
+
 template <int K>
-__global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
+__device__ __forceinline__ void wta_slab_pixel(const WtaView &v, const u32x2 (&w)[2][8], int px, int j)
 {
-    int vi = 0;
-    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
-    const WtaView v = a.v[vi];
-    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
-    const int px = ((int)blockIdx.x - a.blk0[vi]) * WTA_PPB + q;
-    const int npx = v.H * v.W;
-    if (px >= npx) return;
     constexpr int D = 16 * K;
     uint32_t sv[2][4];
     int dd[2][8];
-    slab_sums<K>(v.slab, (size_t)npx * D, px, j, v.nslab, sv, dd);
+    slab_add<K>(w, j, v.nslab, sv, dd);
     uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -263,6 +281,28 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         f.z = (float)smin / (float)(8 * (SF_CMAX + v.P2));
         f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
         reinterpret_cast<float4 *>(v.feat)[px] = f;
+    }
+}
+
+template <int K>
+__global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
+{
+    int vi = 0;
+    while ((int)blockIdx.x >= a.blk0[vi + 1]) ++vi;
+    const WtaView v = a.v[vi];
+    const int q = threadIdx.x >> 4, j = threadIdx.x & 15;
+    const int px0 = ((int)blockIdx.x - a.blk0[vi]) * (WTA_PPB * WTA_G) + q;
+    const int npx = v.H * v.W;
+    constexpr int D = 16 * K;
+    const size_t cells = (size_t)npx * D;
+    u32x2 w[2][2][8];
+    if (px0 < npx) slab_load<K>(v.slab, cells, px0, j, v.nslab, w[0]);
+#pragma unroll
+    for (int g = 0; g < WTA_G; ++g) {
+        const int px = px0 + g * WTA_PPB;
+        if (px >= npx) break;  // uniform across the 16-lane group
+        if (g + 1 < WTA_G && px + WTA_PPB < npx) slab_load<K>(v.slab, cells, px + WTA_PPB, j, v.nslab, w[(g + 1) & 1]);
+        wta_slab_pixel<K>(v, w[g & 1], px, j);
     }
 }
 
@@ -341,7 +381,7 @@ int launch_wta_slabs(WtaArgs &a, hipStream_t st)
     long long tot = 0;
     for (int i = 0; i < a.n; ++i) {
         a.blk0[i] = (int)tot;
-        tot += ((long long)a.v[i].H * a.v[i].W + WTA_PPB - 1) / WTA_PPB;
+        tot += ((long long)a.v[i].H * a.v[i].W + WTA_PPB * WTA_G - 1) / (WTA_PPB * WTA_G);
     }
     for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
     if (tot <= 0) return SF_OK;
