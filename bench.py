@@ -74,7 +74,18 @@ def cpu_baseline(fr, D, runs=3):
             "sample": f"one {W}x{H} D={D} stereo pair (t0 of frame 0): census of both views, both "
                       f"cost volumes, both 8-path aggregations, WTA, sub-pixel, LR check; "
                       f"single thread, median of {runs} runs ({', '.join(f'{x:.2f}' for x in times)} s)",
-            "seconds": dt, "runs_s": times}
+            "seconds": dt, "runs_s": times, "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _gen_pair(arg):
