@@ -362,18 +362,21 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     }
     wl.n = 2;
     if ((rc = launch_wta_slabs(wl, st))) return rc;
+    // The network writes each map's learned mask and masked disparities itself.
     float *logits = reinterpret_cast<float *>(at(p->off_logit));
-    if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st))) return rc;
     float *dsp[2] = {disp0, disp1};
     uint8_t *vld[2] = {valid0, valid1};
+    LrMaskOut mo{};
     for (int t = 0; t < 2; ++t) {
-        const float *dsub = reinterpret_cast<const float *>(at(p->off_dsub[t]));
-        if ((rc = launch_lr_mask(logits + (size_t)t * H * W,
-                                 reinterpret_cast<const int16_t *>(at(p->off_wtal[t])), dsub, H, W,
-                                 vld[t], dsp[t], st)))
-            return rc;
-        if (p->median && (rc = launch_median_mask(dsub, vld[t], H, W, dsp[t], st))) return rc;
+        mo.wta[t] = reinterpret_cast<const int16_t *>(at(p->off_wtal[t]));
+        mo.dsub[t] = reinterpret_cast<const float *>(at(p->off_dsub[t]));
+        mo.valid[t] = vld[t];
+        mo.disp[t] = dsp[t];
     }
+    if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st, &mo))) return rc;
+    if (p->median)
+        for (int t = 0; t < 2; ++t)
+            if ((rc = launch_median_mask(mo.dsub[t], vld[t], H, W, dsp[t], st))) return rc;
     return launch_combine(disp0, valid0, disp1, valid1, flow, H, W, cam, sf4, valid, xyz0, motion, st);
 }
 

@@ -622,7 +622,8 @@ __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi,
 __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__restrict__ frag,
                                                                  const float *__restrict__ fl,
                                                                  const float4 *__restrict__ feat,
-                                                                 int H, int W, float *__restrict__ logits)
+                                                                 int H, int W, float *__restrict__ logits,
+                                                                 LrMaskOut mask)
 {
     constexpr int FH = FT_H + 8, FW = FT_W + 8;   // features
     constexpr int H1 = FT_H + 6, W1 = FT_W + 6;   // a1
@@ -681,7 +682,14 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
         float s = 0.0f;
 #pragma unroll
         for (int t = 0; t < 9; ++t) s += P[t * N3 + (oy + t / 3) * W3 + ox + t % 3];
-        logits[img + (size_t)gy * W + gx] = s + b4;
+        const float logit = s + b4;
+        const size_t i = (size_t)gy * W + gx;
+        logits[img + i] = logit;
+        if (b < 2 && mask.valid[b]) {  // the learned mask of this map, as lr_mask_kernel computes it
+            const int ok = logit > 0.0f && gx - (int)mask.wta[b][i] >= 0;
+            mask.valid[b][i] = (uint8_t)ok;
+            mask.disp[b][i] = ok ? mask.dsub[b][i] : -1.0f;
+        }
     }
 }
 
@@ -781,8 +789,13 @@ static int lr_forward(const float *params, const float *feat, int B, int H, int 
 
 namespace sf {
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
-                  uint8_t *ws, hipStream_t st)
+                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask)
 {
+    LrMaskOut mo{};
+    if (mask) {
+        if (B > 2) return fail(SF_EINVAL, "lrnet_forward: a mask needs at most 2 maps");
+        mo = *mask;
+    }
     const LrLayout L = lr_layout(B, H, W, false);
     uint4 *frag = reinterpret_cast<uint4 *>(ws + L.frag);
     float *fl = reinterpret_cast<float *>(ws + L.fl);
@@ -790,7 +803,7 @@ int lrnet_forward(const float *params, const float *feat, int B, int H, int W, f
     hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_FRAGS / 64), dim3(64), 0, st, params, frag, fl);
     dim3 g((W + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H, B);
     hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(64 * FT_NW), 0, st, frag, fl,
-                       reinterpret_cast<const float4 *>(feat), H, W, logits);
+                       reinterpret_cast<const float4 *>(feat), H, W, logits, mo);
     return launch_status("lrnet_fused_kernel");
 }
 

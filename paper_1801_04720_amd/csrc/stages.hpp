@@ -60,8 +60,16 @@ int launch_wta_diag_slabs(WtaArgs &a, hipStream_t st);  // fills blk0; W <= 4096
 int launch_median_mask(const float *dense, const uint8_t *mask, int H, int W, float *out,
                        hipStream_t st);
 size_t lrnet_forward_ws_bytes(int B, int H, int W);
+// Learned mask written by the network's own last step (maps b < 2): valid =
+// logit > 0 and x - wta >= 0, disp = valid ? dsub : -1 (as launch_lr_mask).
+struct LrMaskOut {
+    const int16_t *wta[2];
+    const float *dsub[2];
+    uint8_t *valid[2];
+    float *disp[2];
+};
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
-                  uint8_t *ws, hipStream_t st);
+                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask = nullptr);
 int launch_lr_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
                    uint8_t *valid, float *disp, hipStream_t st);
 int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
