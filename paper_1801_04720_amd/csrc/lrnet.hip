@@ -10,8 +10,10 @@
 // Flat FP32 parameter vector (5377): W1[16][4][3][3] b1[16] W2[16][16][3][3]
 // b2[16] W3[16][16][3][3] b3[16] W4[1][16][3][3] b4[1].
 //
-// Activations live in HBM as BF16 NHWC ([B][H][W][16], 32 bytes per pixel).
-// Kernels:
+// Inference is one fused kernel per output tile with the activations in LDS
+// (lrnet_fused_kernel, all four layers on MFMA; see "fused inference" below).
+// Training keeps the activations in HBM as BF16 NHWC ([B][H][W][16], 32 bytes
+// per pixel) and runs the kernels:
 //   l1_fwd     4 -> 16 (VALU: K = 36 is too thin for a matrix tile)
 //   conv16     16 -> 16 on MFMA v_mfma_f32_16x16x16_bf16: forward (bias,
 //              ReLU, BF16) or backward-data (transposed, flipped weights; the
