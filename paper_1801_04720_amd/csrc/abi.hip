@@ -58,7 +58,10 @@ extern "C" int sf_prof_enable(int max_launches)
     for (hipEvent_t e : g_prof_pool) hipEventDestroy(e);
     g_prof_pool.assign((size_t)2 * max_launches, nullptr);
     for (auto &e : g_prof_pool)
-        if (hipEventCreate(&e) != hipSuccess) return fail(SF_EHIP, "sf_prof_enable: hipEventCreate");
+        // Timing-only events: no system-scope fence when one is recorded between
+        // two launches of a timed region (sf_prof_query only reads timestamps).
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+            return fail(SF_EHIP, "sf_prof_enable: hipEventCreateWithFlags");
     g_prof_next = 0;
     g_prof_recs.clear();
     g_prof_on = true;
