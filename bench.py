@@ -37,25 +37,141 @@ def kernel_ms(lib, name):
     return tot.value, n.value
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of the aggregation kernel from the committed counter
-    summary, only if the kernel sources are unchanged since it was taken."""
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "sgm_tasks_frame_1242x375_traffic.json")
+# The aggregation kernel and the frame plan that builds its task table.
+TRAFFIC_SOURCES = ["paper_1801_04720_amd/csrc/sgm.hip", "paper_1801_04720_amd/csrc/sgm_tasks.hpp",
+                   "paper_1801_04720_amd/csrc/sf_internal.hpp", "paper_1801_04720_amd/csrc/frame.hip"]
+SWEEP_FRAMES = 2   # frames per tuning in --tuning-sweep; the counters of the last one are kept
+
+
+def tuning_candidates():
+    """The 36 aggregation tunings (chains_per_block, prefetch, order,
+    persistent_per_cu) in the order sf_frame_autotune tries them."""
+    return [(cpb, pf, order, pp) for cpb in (4, 8, 16) for order in (0, 1) for pf in (4, 8)
+            for pp in (0, 4, 8)]
+
+
+def _sources_sha256():
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "sgm_tasks_frame_1242x375_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if not kernel.startswith(rec["kernel"].split("<")[0][: len("sgm_tasks")]):
-        return None
     h = hashlib.sha256()
-    for src in rec["sources"]:
+    for src in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, src), "rb") as f:
             h.update(f.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, tuning):
+    """HBM-side bytes per launch of the aggregation kernel under this tuning
+    (a (chains_per_block, prefetch, order, persistent_per_cu) tuple) from the
+    committed counter table, only if the kernel sources are unchanged since the
+    counters were taken; None otherwise."""
+    if not kernel.startswith("sgm_tasks") or not os.path.exists(TRAFFIC_JSON):
         return None
-    return rec["traffic_bytes_per_launch"]
+    with open(TRAFFIC_JSON) as f:
+        rec = json.load(f)
+    if rec.get("sources") != TRAFFIC_SOURCES or rec.get("sources_sha256") != _sources_sha256():
+        return None
+    e = rec.get("by_tuning", {}).get(",".join(str(v) for v in tuning))
+    return e["traffic_bytes_per_launch"] if e else None
+
+
+def _pmc_per_dispatch(db, counter):
+    """(dispatch id, kernel name, value) of one counter from a rocprofv3 results
+    database, in dispatch order."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    try:
+        return con.execute("select dispatch_id, name, counter_value from pmc_events "
+                           "where counter_name = ? order by dispatch_id", (counter,)).fetchall()
+    finally:
+        con.close()
+
+
+def write_traffic_table(fetch_db, write_db, out=TRAFFIC_JSON):
+    """Turn the FETCH_SIZE and WRITE_SIZE passes over `bench.py --tuning-sweep`
+    into the per-tuning traffic table: each counter is scaled by what it reads
+    for the sweep's own 1 GiB copies (known to move 1 GiB each way)."""
+    f, w = _pmc_per_dispatch(fetch_db, "FETCH_SIZE"), _pmc_per_dispatch(write_db, "WRITE_SIZE")
+    kib = 1 << 20  # KiB in 1 GiB
+
+    def copies(rows):
+        v = sorted((x for _, n, x in rows if "copyBuffer" in n), reverse=True)[:3]
+        if len(v) < 3:
+            raise SystemExit("bench.py: fewer than three 1 GiB copies in the counter pass")
+        return sum(v) / len(v)
+
+    cf, cw = copies(f), copies(w)
+    ff, fw = kib / cf, kib / cw
+    ag_f = [x for _, n, x in f if "sgm_tasks_kernel" in n]
+    ag_w = [x for _, n, x in w if "sgm_tasks_kernel" in n]
+    names = sorted({n.split("(")[0] for _, n, _x in f if "sgm_tasks_kernel" in n})
+    cand = tuning_candidates()
+    if len(ag_f) != SWEEP_FRAMES * len(cand) or len(ag_w) != len(ag_f):
+        raise SystemExit(f"bench.py: expected {SWEEP_FRAMES * len(cand)} aggregation dispatches, "
+                         f"found {len(ag_f)} / {len(ag_w)}")
+    table = {}
+    for i, c in enumerate(cand):
+        k = SWEEP_FRAMES * i + SWEEP_FRAMES - 1
+        table[",".join(str(v) for v in c)] = {
+            "fetch_size_kib": ag_f[k], "write_size_kib": ag_w[k],
+            "traffic_bytes_per_launch": (ag_f[k] * ff + ag_w[k] * fw) * 1024}
+    sweep = "python3 bench.py --tuning-sweep"
+    rec = {"kernels": names,
+           "workload": "plain scene-flow frame 1242x375 D=128, all 4 views in one aggregation launch; "
+                       f"{SWEEP_FRAMES} frames per tuning, counters of the last one",
+           "keys": "chains_per_block,prefetch,order,persistent_per_cu",
+           "sources": TRAFFIC_SOURCES, "sources_sha256": _sources_sha256(),
+           "copy_calibration": {"bytes": 1 << 30, "fetch_size_kib": cf, "write_size_kib": cw,
+                                "fetch_factor": ff, "write_factor": fw},
+           "by_tuning": table,
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmt -o fetch -- {sweep}",
+                        f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmt -o write -- {sweep}",
+                        "python3 bench.py --traffic-from gpurun_out/pmt/fetch_results.db "
+                        "gpurun_out/pmt/write_results.db"]}
+    with open(out, "w") as fo:
+        json.dump(rec, fo, indent=1)
+    tb = [e["traffic_bytes_per_launch"] / 1e9 for e in table.values()]
+    print(json.dumps({"traffic_table": out, "tunings": len(table), "GB_min": min(tb),
+                      "GB_max": max(tb)}), flush=True)
+
+
+def bench_tuning_sweep(args, dev):
+    """Three 1 GiB device copies (the calibration kernel), then SWEEP_FRAMES plain
+    1242x375/128 frames for every aggregation tuning: the program the FETCH_SIZE
+    and WRITE_SIZE passes of the traffic table run."""
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import synth
+    from paper_1801_04720_amd._lib import SfAggTuning
+    from paper_1801_04720_amd.pipeline import FusedFrame
+
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=dev)
+    b = torch.empty(n, dtype=torch.uint8, device=dev)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    H, W, D = 375, 1242, 128
+    fr = synth.frame_1242x375(0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    inputs = [t(fr.t0.left), t(fr.t0.right), t(fr.t1.left), t(fr.t1.right), t(fr.flow)]
+    torch.cuda.synchronize()
+    cand = tuning_candidates()
+    for i, c in enumerate(cand):
+        pipe = FusedFrame(H, W, D, tuning=SfAggTuning(*c), device=dev)
+        for _ in range(SWEEP_FRAMES):
+            pipe.run(*inputs)
+        torch.cuda.synchronize()
+        del pipe
+        if i % 6 == 5:
+            print(f"tuning sweep: {i + 1}/{len(cand)} tunings", flush=True)
+    print(json.dumps({"tuning_sweep": cand, "frames_per_tuning": SWEEP_FRAMES, "copy_bytes": n,
+                      "copies": 3}), flush=True)
 
 
 def cpu_baseline(fr, D, runs=3):
@@ -654,6 +770,12 @@ def main():
     ap.add_argument("--peaks", action="store_true",
                     help="only measure the HBM / last-level-cache stream rates and the packed "
                          "16-bit VALU rate, and exit")
+    ap.add_argument("--tuning-sweep", action="store_true",
+                    help="only run three 1 GiB copies and two plain frames per aggregation tuning "
+                         "(the program of the FETCH_SIZE / WRITE_SIZE passes), and exit")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the per-tuning traffic table from the rocprofv3 databases of the "
+                         "two counter passes over --tuning-sweep, and exit (no GPU needed)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference kernel "
                          "for scaling FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -662,6 +784,8 @@ def main():
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the path shards per stereo pair / frame, see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_from:
+        return write_traffic_table(*args.traffic_from)
 
     import numpy as np
     import torch
@@ -673,6 +797,8 @@ def main():
     dev = "cuda:0"
     if args.peaks:
         return bench_peaks(args, dev)
+    if args.tuning_sweep:
+        return bench_tuning_sweep(args, dev)
     if args.copy_calibration:
         n = 1 << 30
         a = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -707,6 +833,11 @@ def main():
     for _ in range(args.warmup):
         pipe.run(L0, R0, L1, R1, flow)
     torch.cuda.synchronize()
+    # The tuning the fused plan runs (the plan's default when none is given).
+    if tuning is not None:
+        tuning_key = (tuning.chains_per_block, tuning.prefetch, tuning.order, tuning.persistent_per_cu)
+    else:
+        tuning_key = (16, 8, 0, 8 if args.pipeline == "persistent" else 0)
 
     # Dominant kernel: the path aggregation (one launch for all 4 views, or one per view).
     kname, views_per_launch = ("sgm_paths", 1) if args.pipeline == "stages" else ("sgm_tasks", 4)
@@ -746,7 +877,8 @@ def main():
     achieved = ops / avg_s / 1e12
     roofline = {"bound": "alu", "kernel": kname, "achieved": achieved,
                 "peak": PEAK_U16_TOPS, "unit": "TOP/s (packed u16)",
-                "frac": achieved / PEAK_U16_TOPS, "traffic": measured_traffic(kname),
+                "frac": achieved / PEAK_U16_TOPS,
+                "traffic": measured_traffic(kname, tuning_key),
                 "ops_per_launch": ops, "avg_launch_ms": sg["avg_ms"], "timed_launches": sg["launches"],
                 "gcups_per_launch": cells * views_per_launch / avg_s / 1e9}
     if roofline["traffic"]:
