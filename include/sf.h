@@ -192,7 +192,10 @@ int sf_combine(const float *disp0, const uint8_t *valid0, const float *disp1,
  * lays out the caller's workspace, whose size sf_plan_workspace_bytes reports.
  * Runs allocate nothing and enqueue only kernel launches, so they can be
  * captured in a HIP graph.  A plan may be run concurrently on different
- * streams only with different workspaces. */
+ * streams only with different workspaces, and only if its aggregation tuning
+ * is not persistent: persistent launches pull tasks from a counter in the
+ * plan's buffer, which each launch leaves at zero for the next one, so runs of
+ * such a plan must follow one another (one stream, or ordered by events). */
 typedef struct sf_plan_s *sf_plan;
 
 /* Tuning of the multi-view aggregation launch (frame and batch plans):

@@ -441,6 +441,7 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
             if (hipMalloc(&tab, bv + bt + 256) != hipSuccess) { rc = fail(SF_EHIP, "sf_agg_autotune: hipMalloc"); break; }
             hipMemcpy(tab, views.data(), views.size() * sizeof(AggView), hipMemcpyHostToDevice);
             hipMemcpy(tab + bv, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice);
+            hipMemset(tab + bv + bt, 0, sizeof(int));  // the persistent counter starts at 0
             for (int pf : prefs)
                 for (int pp : pers) {
                     auto go = [&]() {

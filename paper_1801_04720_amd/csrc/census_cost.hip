@@ -1,6 +1,7 @@
 // Census transform and Hamming matching-cost volume (the matching cost inside
 // SGM, paper Sec. 3.1; the 9x7 census and Hamming distance are the workload's
 // choice, the paper names no cost).
+#include "lrnet_pack.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
 
@@ -27,6 +28,12 @@ constexpr int CEN_LH = CEN_TH + 2 * CEN_RY;        // LDS rows
 // LDS with clamp-to-edge.
 __global__ __launch_bounds__(CEN_TX *CEN_TH) void census_kernel(CensusArgs a)
 {
+    if ((int)blockIdx.z == a.n) {  // the extra plane: the network's weight fragments
+        const int nb = gridDim.x * gridDim.y;
+        for (int s = (blockIdx.y * gridDim.x + blockIdx.x) * CEN_TH + threadIdx.y; s < FP_NSLOT; s += nb * CEN_TH)
+            lrnet_pack_lane(a.pack_prm, a.pack_frag, a.pack_fl, s, threadIdx.x);
+        return;
+    }
     const int H = a.H, W = a.W, pitch = a.pitch[blockIdx.z];
     const uint8_t *__restrict__ img = a.img[blockIdx.z];
     uint64_t *__restrict__ out = a.out[blockIdx.z];
@@ -276,7 +283,8 @@ static inline size_t cv_lds_bytes(int D)
 
 int launch_census(const CensusArgs &a, hipStream_t st)
 {
-    dim3 grid((a.W + CEN_TW - 1) / CEN_TW, (a.H + CEN_TH - 1) / CEN_TH, a.n);
+    if (a.pack_prm && a.n >= STAGE_MAXV) return fail(SF_EINVAL, "launch_census: no plane left for packing");
+    dim3 grid((a.W + CEN_TW - 1) / CEN_TW, (a.H + CEN_TH - 1) / CEN_TH, a.n + (a.pack_prm ? 1 : 0));
     ProfScope prof("census", st);
     hipLaunchKernelGGL(census_kernel, grid, dim3(CEN_TX, CEN_TH), 0, st, a);
     return launch_status("census_kernel");

@@ -33,7 +33,8 @@ int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::ve
     p.d_tasks = reinterpret_cast<AggTask *>(static_cast<uint8_t *>(p.d_tables) + align256(bv));
     p.d_counter = reinterpret_cast<int *>(static_cast<uint8_t *>(p.d_tables) + align256(bv) + bt);
     if (hipMemcpy(p.d_views, views.data(), bv, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p.d_tasks, tasks.data(), bt, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(p.d_tasks, tasks.data(), bt, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(p.d_counter, 0, sizeof(int)) != hipSuccess)  // the persistent launches keep it at 0
         return fail(SF_EHIP, "plan: upload of the task table failed");
     return SF_OK;
 }
@@ -324,6 +325,9 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     CensusArgs ca{};
     for (int i = 0; i < 4; ++i) { ca.img[i] = img[i]; ca.out[i] = cen[i]; ca.pitch[i] = pitch; }
     ca.n = 4; ca.H = H; ca.W = W;
+    // The census launch also packs the network's weight fragments (one launch fewer).
+    ca.pack_prm = lr_params;
+    lrnet_pack_targets(at(p->off_lrws), &ca.pack_frag, &ca.pack_fl);
     int rc = launch_census(ca, st);
     if (rc) return rc;
     // Left-base cost volumes only: views 0 = L0 base, 1 = L1 base.
@@ -373,7 +377,7 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
         mo.valid[t] = vld[t];
         mo.disp[t] = dsp[t];
     }
-    if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st, &mo))) return rc;
+    if ((rc = lrnet_forward(lr_params, feat, 2, H, W, logits, at(p->off_lrws), st, &mo, true))) return rc;
     if (p->median)
         for (int t = 0; t < 2; ++t)
             if ((rc = launch_median_mask(mo.dsub[t], vld[t], H, W, dsp[t], st))) return rc;

@@ -23,26 +23,16 @@
 //   wgrad      dW[co][ci][tap] = sum_p gz[co](p) a[ci](p + tap - 1) on MFMA
 //              (K = pixels), per-block partials reduced in a fixed order
 //   adam       FP32 Adam step.
+#include "lrnet_pack.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
 
 namespace sf {
 
-constexpr int LR_NP = 5377;
-constexpr int OFF_W1 = 0, OFF_B1 = 576, OFF_W2 = 592, OFF_B2 = 2896, OFF_W3 = 2912, OFF_B3 = 5216,
-              OFF_W4 = 5232, OFF_B4 = 5376;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
-__device__ __forceinline__ uint16_t bf16_bits(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u | ((u & 0x7fffffu) ? 0x400000u : 0u)) >> 16);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
 // The same rounding for a value that is not NaN (a ReLU output): no branch;
 // exact for every other input, infinities included.
 __device__ __forceinline__ uint16_t bf16_bits_nonnan(float f)
@@ -494,13 +484,11 @@ __global__ void lr_mask_kernel(const float *__restrict__ logits, const int16_t *
 // channel) puts its 9 taps on the rows of A: one MFMA per 16 pixels gives the
 // per-tap channel sums P_t(p), which go to LDS, and the logit at p is
 // b4 + sum over taps t of P_t(p + offset_t).  Weight fragments come pre-packed
-// per lane (pack_fused_kernel), 16 bytes per lane and slot; each block copies
-// them to LDS while its features load.
+// per lane (lrnet_pack_lane: pack_fused_kernel, or the learned frame's census
+// launch), 16 bytes per lane and slot; each block copies them to LDS while its
+// features load.
 constexpr int FT_H = 16, FT_W = 32;
 constexpr int FT_NW = 16;  // waves per block: they share the tile's LDS, so more of them hide latency
-constexpr int FP_L1 = 0, FP_L2 = 2, FP_L3 = 7, FP_L4 = 12, FP_NSLOT = 13;  // uint4 slots of 64 lanes
-constexpr int FP_FRAGS = FP_NSLOT * 64;
-constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_B4 = 48, FP_FLOATS = 49;
 
 typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -519,39 +507,7 @@ __device__ __forceinline__ int tap_off(int t, int wi) { return (t / 3) * wi + t 
 __global__ void pack_fused_kernel(const float *__restrict__ prm, uint4 *__restrict__ frag,
                                   float *__restrict__ fl)
 {
-    const int lane = threadIdx.x & 63;
-    const int slot = blockIdx.x;  // 0 .. FP_NSLOT - 1
-    const int n = lane & 15, kg = lane >> 4;
-    uint16_t h[8];
-    for (int j = 0; j < 8; ++j) {
-        const int i = j & 3, hi = j >> 2;
-        float w = 0.0f;
-        if (slot == FP_L1) {  // layer 1, taps kg and kg + 4, input channel i
-            w = prm[OFF_W1 + (n * 4 + i) * 9 + kg + 4 * hi];
-        } else if (slot == FP_L1 + 1) {  // layer 1, tap 8 (lane group 0 only)
-            if (kg == 0 && !hi) w = prm[OFF_W1 + (n * 4 + i) * 9 + 8];
-        } else if (slot < FP_L4) {  // layers 2, 3: taps 2q, 2q + 1 (q < 4) or tap 8, channel 4 kg + i
-            const int q = (slot - FP_L2) % 5;
-            const int off = slot < FP_L3 ? OFF_W2 : OFF_W3;
-            if (q < 4) w = prm[off + (n * 16 + 4 * kg + i) * 9 + 2 * q + hi];
-            else if (!hi) w = prm[off + (n * 16 + 4 * kg + i) * 9 + 8];
-        } else if (n < 9 && !hi) {  // layer 4: row n = tap n, input channel 4 kg + i
-            w = prm[OFF_W4 + (4 * kg + i) * 9 + n];
-        }
-        h[j] = bf16_bits(w);
-    }
-    frag[slot * 64 + lane] = make_uint4((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
-                                        (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16));
-    if (slot == 0) {
-        for (int i = lane; i < FP_FLOATS; i += 64) {
-            float v;
-            if (i < 16) v = prm[OFF_B1 + i];
-            else if (i < 32) v = prm[OFF_B2 + i - 16];
-            else if (i < 48) v = prm[OFF_B3 + i - 32];
-            else v = prm[OFF_B4];
-            fl[i] = v;
-        }
-    }
+    lrnet_pack_lane(prm, frag, fl, blockIdx.x, threadIdx.x & 63);
 }
 
 // Offset (in BF16 elements) of channels 4 kg .. 4 kg + 3 of pixel p in a
@@ -790,8 +746,15 @@ static int lr_forward(const float *params, const float *feat, int B, int H, int 
 }
 
 namespace sf {
+void lrnet_pack_targets(uint8_t *ws, uint4 **frag, float **fl)
+{
+    const LrLayout L = lr_layout(1, 1, 1, false);  // the fragments do not depend on B, H, W
+    *frag = reinterpret_cast<uint4 *>(ws + L.frag);
+    *fl = reinterpret_cast<float *>(ws + L.fl);
+}
+
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
-                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask)
+                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask, bool prepacked)
 {
     LrMaskOut mo{};
     if (mask) {
@@ -802,7 +765,8 @@ int lrnet_forward(const float *params, const float *feat, int B, int H, int W, f
     uint4 *frag = reinterpret_cast<uint4 *>(ws + L.frag);
     float *fl = reinterpret_cast<float *>(ws + L.fl);
     ProfScope prof("lrnet_fused", st);
-    hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_FRAGS / 64), dim3(64), 0, st, params, frag, fl);
+    if (!prepacked)
+        hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_NSLOT), dim3(64), 0, st, params, frag, fl);
     dim3 g((W + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H, B);
     hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(64 * FT_NW), 0, st, frag, fl,
                        reinterpret_cast<const float4 *>(feat), H, W, logits, mo);

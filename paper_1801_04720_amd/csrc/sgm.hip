@@ -405,8 +405,11 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
 
 // Many views from a task table (all tasks of one launch share K = D / 16).
 // A block of 16 * c threads runs one task of up to c chains.  persistent:
-// gridDim.x blocks pull task indices from *counter (zeroed before the launch)
-// until the table is done; otherwise block b runs task b.
+// gridDim.x (<= ntasks) blocks pull task indices from *counter until the table
+// is done; otherwise block b runs task b.  The counter must be 0 at the launch
+// and is 0 again when the launch ends: every block pulls exactly one index >=
+// ntasks, on its way out, so the block that pulls ntasks + gridDim.x - 1 makes
+// the launch's last pull and resets it (no clearing launch between frames).
 template <int K, int U, bool ADAPT>
 __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
                                                            const AggTask *__restrict__ tasks,
@@ -423,7 +426,10 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
             ti = __builtin_amdgcn_readfirstlane(s_task);
             __syncthreads();
         }
-        if (ti >= ntasks) return;
+        if (ti >= ntasks) {
+            if (counter && threadIdx.x == 0 && ti == ntasks + (int)gridDim.x - 1) atomicExch(counter, 0);
+            return;
+        }
         const AggTask tk = tasks[ti];
         const AggView &v = views[tk.view];
         if (q < tk.nlines) {
@@ -589,8 +595,7 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
     int nb = ntasks;
     int *counter = nullptr;
     if (persistent_blocks > 0) {
-        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st,
-                           reinterpret_cast<uint32_t *>(d_counter), (size_t)1, 0u);
+        // *d_counter is 0 here: zeroed with the table and reset by every launch.
         nb = persistent_blocks < ntasks ? persistent_blocks : ntasks;
         counter = d_counter;
     }
@@ -607,7 +612,11 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
     case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
     default: return fail(SF_EUNSUPPORTED, "launch_agg_tasks: unsupported K");
     }
-    return launch_status("sgm_tasks_kernel");
+    const int rc = launch_status("sgm_tasks_kernel");
+    if (rc && counter)  // the launch did not run: leave the counter at 0 for the next one
+        hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t *>(counter),
+                           (size_t)1, 0u);
+    return rc;
 }
 
 }  // namespace sf

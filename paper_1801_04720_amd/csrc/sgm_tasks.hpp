@@ -40,7 +40,8 @@ void append_agg_tasks(std::vector<AggTask> &tasks, std::vector<int> &task_len, i
                       const AggView &v, int chains_per_task = 16);
 void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int> &task_len);
 // persistent_blocks > 0: persistent launch with that many blocks pulling from
-// *d_counter (reset on the stream first); 0: one block per task.
+// *d_counter, which must be 0 before the first launch (the kernel leaves it at
+// 0 again); 0: one block per task.  Launches sharing a counter must not overlap.
 // chains_per_block in {4, 8, 16} must match the table's chains per task;
 // prefetch (cost steps in flight per chain) in {4, 8}.
 // images: NULL or n = 0 for the constant P2; otherwise every view index of the

@@ -17,6 +17,11 @@ struct CensusArgs {
     uint64_t *out[STAGE_MAXV];
     int pitch[STAGE_MAXV];
     int n, H, W;
+    // Optional extra job (pack_prm != NULL, n < STAGE_MAXV): pack the network's
+    // weight fragments from pack_prm into the targets of lrnet_pack_targets.
+    const float *pack_prm;
+    uint4 *pack_frag;
+    float *pack_fl;
 };
 
 struct CostArgs {
@@ -68,8 +73,13 @@ struct LrMaskOut {
     uint8_t *valid[2];
     float *disp[2];
 };
+// Where the inference workspace holds the packed weight fragments.
+void lrnet_pack_targets(uint8_t *ws, uint4 **frag, float **fl);
+// prepacked: the fragments in ws already hold params (packed by an earlier
+// launch on the stream), so no packing launch precedes the network's.
 int lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
-                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask = nullptr);
+                  uint8_t *ws, hipStream_t st, const LrMaskOut *mask = nullptr,
+                  bool prepacked = false);
 int launch_lr_mask(const float *logits, const int16_t *wta, const float *dsub, int H, int W,
                    uint8_t *valid, float *disp, hipStream_t st);
 int launch_combine(const float *disp0, const uint8_t *valid0, const float *disp1,

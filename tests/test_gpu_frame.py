@@ -83,14 +83,20 @@ def test_fused_equals_stagewise_and_persistent_1242x375():
 
 
 def test_fused_frame_repeatable():
-    say("fused frame run twice")
+    """A persistent plan run four times in a row (its task counter returns to
+    zero at the end of every launch, with no clearing launch in between) equals
+    the one-block-per-task plan every time."""
+    say("fused persistent frame run four times")
     fr = synth.frame_planar(synth.rng_for(8, 5), 64, 200, 64, 30.0)
-    ff = FusedFrame(64, 200, 64, persistent=True, device=DEV)
     args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
-    a = {k: host(v).copy() for k, v in ff.run(*args).items()}
-    b = {k: host(v).copy() for k, v in ff.run(*args).items()}
-    for k in a:
-        assert np.array_equal(a[k], b[k], equal_nan=True), k
+    ref = {k: host(v).copy() for k, v in FusedFrame(64, 200, 64, device=DEV).run(*args).items()}
+    ff = FusedFrame(64, 200, 64, persistent=True, device=DEV)
+    for rep in range(4):
+        for v in ff.out.values():
+            v.fill_(7)
+        got = {k: host(v).copy() for k, v in ff.run(*args).items()}
+        for k in ref:
+            assert np.array_equal(got[k], ref[k], equal_nan=True), (rep, k)
 
 
 def test_learned_frame_equals_stagewise(orc):
