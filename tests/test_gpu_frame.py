@@ -2,6 +2,7 @@
 entry point (all four aggregations in one launch, slabs summed inside WTA),
 its persistent variant, and the per-stage path, at a small size and at the
 full 1242x375 / D=128 size."""
+import ctypes as ct
 import os
 import sys
 
@@ -80,6 +81,46 @@ def test_fused_equals_stagewise_and_persistent_1242x375():
     assert np.array_equal(a["disp1"], host(m1["disp"]))
     for k in ("sf4", "valid", "xyz0", "motion"):
         assert np.array_equal(a[k], host(c[k]), equal_nan=True), k
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_frame_images_at_odd_offsets_and_pitch(learned):
+    """The four images inside wider rows (pitch W + 13) at byte offsets 1, 2, 3
+    and 5 give the same frame as compact copies: the census launch stages image
+    rows with aligned reads (interior tiles at this width) or byte by byte (the
+    row ends), for any alignment, and every later stage reads the images (the
+    learned features) with the same pitch."""
+    from paper_1801_04720_amd import lrnet
+
+    say("frame with odd image offsets and pitch, learned =", learned)
+    H, W, D = 40, 800, 128
+    fr = synth.frame_planar(synth.rng_for(8, 43), H, W, D, 20.0)
+    imgs = [fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right]
+    compact = [dev(a) for a in imgs]
+    wide = []
+    for a, off in zip(imgs, (1, 2, 3, 5)):
+        buf = np.full((H, W + 13), 77, np.uint8)
+        buf[:, off:off + W] = a
+        wide.append(dev(buf)[:, off:off + W])
+    assert wide[0].stride(0) == W + 13
+    flow = dev(fr.flow)
+    prm = dev(lrnet.init_params(3)) if learned else None
+    ref = {k: host(v).copy() for k, v in FusedFrame(H, W, D, learned_params=prm, device=DEV).run(*compact, flow).items()}
+    # The pitch is a C-ABI argument (the Python binding takes compact tensors).
+    ff = FusedFrame(H, W, D, learned_params=prm, device=DEV)
+    P = lambda t: ct.c_void_p(t.data_ptr())  # noqa: E731
+    o = ff.out
+    cam = ct.byref(_lib.SfCamera(*[float(c) for c in ff.cam]))
+    head = [ff.plan.handle] + [P(a) for a in wide] + [W + 13, P(flow), cam]
+    tail = [P(o[k]) for k in ("disp0", "valid0", "disp1", "valid1", "sf4", "valid", "xyz0", "motion")]
+    tail += [P(ff.ws), ff.ws.numel(), None]
+    if learned:
+        _lib.check(_lib.lib().sf_frame_run_learned(*head, P(prm), *tail))
+    else:
+        _lib.check(_lib.lib().sf_frame_run(*head, *tail))
+    torch.cuda.synchronize()
+    for k in ref:
+        assert np.array_equal(host(o[k]), ref[k], equal_nan=True), k
 
 
 def test_fused_frame_repeatable():
