@@ -226,13 +226,37 @@ __device__ __forceinline__ float subpixel(int ds, int D, uint32_t av, uint32_t s
     return sub;
 }
 
-// Each 16-lane group takes WTA_G pixels WTA_PPB apart; the slabs of the next
-// pixel are loaded while the current one is reduced, so the loads of a wave
-// stay in flight across its arithmetic.
-constexpr int WTA_G = 4;
+constexpr int WTA_G = 4;  // pixels per 16-lane group (see wta_slab_kernel)
 
-template <int K>
-__device__ __forceinline__ void wta_slab_pixel(const WtaView &v, const u32x2 (&w)[2][8], int px, int j)
+// What a launch of the slab WTA computes (one mode per launch, so that no load
+// sits behind a runtime branch: the compiler then counts every load on every
+// path and each wait covers only the loads it needs).
+enum WtaMode : int {
+    WM_RIGHT = 0,  // d* only (right views)
+    WM_LEFT = 1,   // d*, sub-pixel disparity, valid := 1 (no right map)
+    WM_LR = 2,     // ... and the LR check against wta_r
+    WM_FEAT = 3,   // WM_LEFT and the network features (no right map)
+    WM_FEAT_LR = 4 // WM_LR and the features
+};
+
+__host__ __device__ constexpr bool wm_lr(int m) { return m == WM_LR || m == WM_FEAT_LR; }
+__host__ __device__ constexpr bool wm_feat(int m) { return m == WM_FEAT || m == WM_FEAT_LR; }
+
+static int wta_mode(const WtaView &v)
+{
+    if (v.right_only) return WM_RIGHT;
+    if (v.feat) return v.wta_r ? WM_FEAT_LR : WM_FEAT;
+    return v.wta_r ? WM_LR : WM_LEFT;
+}
+
+// Result of one pixel's reduction, the same in every lane of its group.
+struct WtaPx {
+    int ds;                     // d*
+    uint32_t smin, av, cv, s2;  // S(d*), S(d* - 1), S(d* + 1), min over |d - d*| >= 2
+};
+
+template <int K, int MODE>
+__device__ __forceinline__ WtaPx wta_reduce(const WtaView &v, const u32x2 (&w)[2][8], int j)
 {
     constexpr int D = 16 * K;
     uint32_t sv[2][4];
@@ -246,45 +270,55 @@ __device__ __forceinline__ void wta_slab_pixel(const WtaView &v, const u32x2 (&w
             for (int e = 0; e < 8; ++e) best = min(best, (sv_val(sv, i, e) << 9) | (uint32_t)dd[i][e]);
         }
     const uint32_t key = row16_min(best);
-    const int ds = (int)(key & 511u);
-    const uint32_t smin = key >> 9;
-    if (v.right_only) {
-        if (j == 0) v.wta[px] = (int16_t)ds;
-        return;
-    }
-    uint32_t av, cv, s2;
-    if (v.feat)
-        neighbours<K, true>(sv, dd, j, ds, av, cv, s2);
-    else
-        neighbours<K, false>(sv, dd, j, ds, av, cv, s2);
-    if (j != 0) return;
-    const int y = px / v.W, x = px - y * v.W;
-    const float sub = subpixel(ds, D, av, smin, cv);
-    int ok = 1;
-    if (v.wta_r) {
-        const int qx = x - ds;
-        ok = 0;
-        if (qx >= 0) {
-            int diff = ds - (int)v.wta_r[(size_t)y * v.W + qx];
+    WtaPx r;
+    r.ds = (int)(key & 511u);
+    r.smin = key >> 9;
+    r.av = r.cv = 0;
+    r.s2 = 0xFFFFFFFFu;
+    if constexpr (MODE != WM_RIGHT) neighbours<K, wm_feat(MODE)>(sv, dd, j, r.ds, r.av, r.cv, r.s2);
+    return r;
+}
+
+// Stores of one pixel (lane 0): d*, and unless right-only the sub-pixel
+// disparity, the LR check with the right map's value rq at x - d*, and the
+// features (inten: the base image byte at the pixel).
+template <int K, int MODE>
+__device__ __forceinline__ void wta_finish(const WtaView &v, const WtaPx &r, int px, int x, int rq,
+                                           uint32_t inten)
+{
+    constexpr int D = 16 * K;
+    if constexpr (MODE == WM_RIGHT) {
+        v.wta[px] = (int16_t)r.ds;
+    } else {
+        const float sub = subpixel(r.ds, D, r.av, r.smin, r.cv);
+        int ok = 1;
+        if constexpr (wm_lr(MODE)) {
+            int diff = r.ds - rq;
             diff = diff < 0 ? -diff : diff;
-            ok = diff <= v.tol;
+            ok = (x - r.ds >= 0) && diff <= v.tol;
         }
-    }
-    if (v.wta) v.wta[px] = (int16_t)ds;
-    v.disp[px] = (ok || v.dense) ? sub : -1.0f;
-    v.valid[px] = (uint8_t)ok;
-    if (v.feat) {
-        if (s2 == 0xFFFFFFFFu) s2 = smin;
-        float4 f;
-        f.x = (float)v.img[(size_t)y * v.pitch + x] / 255.0f;
-        f.y = D > 1 ? (float)ds / (float)(D - 1) : 0.0f;
-        f.z = (float)smin / (float)(8 * (SF_CMAX + v.P2));
-        f.w = (float)s2 / (float)(smin > 1 ? smin : 1u);
-        reinterpret_cast<float4 *>(v.feat)[px] = f;
+        if (v.wta) v.wta[px] = (int16_t)r.ds;
+        v.disp[px] = (ok || v.dense) ? sub : -1.0f;
+        v.valid[px] = (uint8_t)ok;
+        if constexpr (wm_feat(MODE)) {
+            const uint32_t s2 = r.s2 == 0xFFFFFFFFu ? r.smin : r.s2;
+            float4 f;
+            f.x = (float)inten / 255.0f;
+            f.y = D > 1 ? (float)r.ds / (float)(D - 1) : 0.0f;
+            f.z = (float)r.smin / (float)(8 * (SF_CMAX + v.P2));
+            f.w = (float)s2 / (float)(r.smin > 1 ? r.smin : 1u);
+            reinterpret_cast<float4 *>(v.feat)[px] = f;
+        }
     }
 }
 
-template <int K>
+// Each 16-lane group takes WTA_G pixels WTA_PPB apart, software-pipelined: the
+// slabs (and image byte) of pixel g + 1 are loaded while pixel g is reduced,
+// and pixel g's right-map value is loaded before pixel g - 1 is finished, so a
+// wait for it never also waits for the next pixel's slabs (loads complete in
+// issue order).  Past the end of the view the group re-reads its last pixel
+// and stores nothing, so every load is issued on every path.
+template <int K, int MODE>
 __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 {
     int vi = 0;
@@ -295,15 +329,43 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
     const int npx = v.H * v.W;
     constexpr int D = 16 * K;
     const size_t cells = (size_t)npx * D;
+    if (px0 >= npx) return;  // uniform across the 16-lane group (px0 < npx for all in all but the last block)
     u32x2 w[2][2][8];
-    if (px0 < npx) slab_load<K>(v.slab, cells, px0, j, v.nslab, w[0]);
+    uint32_t inten[2] = {0u, 0u};
+    auto load_inten = [&](int p) -> uint32_t {
+        const int y = p / v.W, x = p - y * v.W;
+        return v.img[(size_t)y * v.pitch + x];
+    };
+    slab_load<K>(v.slab, cells, px0, j, v.nslab, w[0]);
+    if constexpr (wm_feat(MODE)) inten[0] = load_inten(px0);
+    WtaPx prev{};
+    int prev_px = 0, prev_x = 0, prev_rq = 0;
+    uint32_t prev_in = 0u;  // inten of the previous pixel (its slot is reused by the prefetch)
 #pragma unroll
     for (int g = 0; g < WTA_G; ++g) {
-        const int px = px0 + g * WTA_PPB;
-        if (px >= npx) break;  // uniform across the 16-lane group
-        if (g + 1 < WTA_G && px + WTA_PPB < npx) slab_load<K>(v.slab, cells, px + WTA_PPB, j, v.nslab, w[(g + 1) & 1]);
-        wta_slab_pixel<K>(v, w[g & 1], px, j);
+        const int px = min(px0 + g * WTA_PPB, npx - 1);
+        if (g + 1 < WTA_G) {
+            const int pn = min(px0 + (g + 1) * WTA_PPB, npx - 1);
+            slab_load<K>(v.slab, cells, pn, j, v.nslab, w[(g + 1) & 1]);
+            if constexpr (wm_feat(MODE)) inten[(g + 1) & 1] = load_inten(pn);
+            // Keep these loads ahead of pixel g's reduction (the scheduler would
+            // otherwise sink them below its waits).
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const WtaPx r = wta_reduce<K, MODE>(v, w[g & 1], j);
+        const int y = px / v.W, x = px - y * v.W;
+        int rq = 0;
+        if constexpr (wm_lr(MODE)) rq = v.wta_r[(size_t)y * v.W + max(x - r.ds, 0)];
+        if (g > 0 && j == 0 && px0 + (g - 1) * WTA_PPB < npx)
+            wta_finish<K, MODE>(v, prev, prev_px, prev_x, prev_rq, prev_in);
+        prev = r;
+        prev_px = px;
+        prev_x = x;
+        prev_rq = rq;
+        prev_in = inten[g & 1];
     }
+    if (j == 0 && px0 + (WTA_G - 1) * WTA_PPB < npx)
+        wta_finish<K, MODE>(v, prev, prev_px, prev_x, prev_rq, prev_in);
 }
 
 // Left WTA and the right map by diagonal search in one pass over the left
@@ -376,32 +438,63 @@ __global__ __launch_bounds__(DIAG_NT) void wta_diag_slab_kernel(WtaArgs a)
     }
 }
 
+template <int K>
+static void launch_wta_slab_mode(int mode, unsigned nblk, const WtaArgs &a, hipStream_t st)
+{
+    switch (mode) {
+    case WM_RIGHT: hipLaunchKernelGGL((wta_slab_kernel<K, WM_RIGHT>), dim3(nblk), dim3(WTA_NT), 0, st, a); break;
+    case WM_LEFT: hipLaunchKernelGGL((wta_slab_kernel<K, WM_LEFT>), dim3(nblk), dim3(WTA_NT), 0, st, a); break;
+    case WM_LR: hipLaunchKernelGGL((wta_slab_kernel<K, WM_LR>), dim3(nblk), dim3(WTA_NT), 0, st, a); break;
+    case WM_FEAT: hipLaunchKernelGGL((wta_slab_kernel<K, WM_FEAT>), dim3(nblk), dim3(WTA_NT), 0, st, a); break;
+    default: hipLaunchKernelGGL((wta_slab_kernel<K, WM_FEAT_LR>), dim3(nblk), dim3(WTA_NT), 0, st, a); break;
+    }
+}
+
+// One launch per run of consecutive views with the same mode (in practice all
+// views of a call share it).  Fills a.blk0 for the last launch's views.
 int launch_wta_slabs(WtaArgs &a, hipStream_t st)
 {
-    long long tot = 0;
-    for (int i = 0; i < a.n; ++i) {
-        a.blk0[i] = (int)tot;
-        tot += ((long long)a.v[i].H * a.v[i].W + WTA_PPB * WTA_G - 1) / (WTA_PPB * WTA_G);
-    }
-    for (int i = a.n; i <= STAGE_MAXV; ++i) a.blk0[i] = (int)tot;
-    if (tot <= 0) return SF_OK;
-    if (tot > 0x7FFFFFFFLL) return fail(SF_EINVAL, "launch_wta_slabs: grid too large");
     for (int i = 0; i < a.n; ++i) {
         if (a.v[i].D != a.v[0].D) return fail(SF_EINVAL, "launch_wta_slabs: views of one launch need one D");
         if (a.v[i].nslab < 1 || a.v[i].nslab > 8) return fail(SF_EINVAL, "launch_wta_slabs: nslab must be in [1, 8]");
+        if (a.v[i].feat && !a.v[i].img) return fail(SF_EINVAL, "launch_wta_slabs: features need the base image");
     }
-    ProfScope prof(a.v[0].right_only ? "wta_slab_right" : "wta_slab_left", st);
-    switch (a.v[0].D / 16) {
-#define SF_WTA_CASE(KK)                                                                             \
-    case KK:                                                                                        \
-        hipLaunchKernelGGL(wta_slab_kernel<KK>, dim3((unsigned)tot), dim3(WTA_NT), 0, st, a);        \
-        break;
-        SF_WTA_CASE(2) SF_WTA_CASE(4) SF_WTA_CASE(6) SF_WTA_CASE(8) SF_WTA_CASE(10) SF_WTA_CASE(12)
-        SF_WTA_CASE(14) SF_WTA_CASE(16)
-#undef SF_WTA_CASE
-    default: return fail(SF_EUNSUPPORTED, "launch_wta_slabs: unsupported D");
+    const int K = a.v[0].D / 16;
+    if (K != 2 && K != 4 && K != 6 && K != 8 && K != 10 && K != 12 && K != 14 && K != 16)
+        return fail(SF_EUNSUPPORTED, "launch_wta_slabs: unsupported D");
+    for (int i0 = 0; i0 < a.n;) {
+        const int mode = wta_mode(a.v[i0]);
+        int i1 = i0 + 1;
+        while (i1 < a.n && wta_mode(a.v[i1]) == mode) ++i1;
+        WtaArgs g{};
+        long long tot = 0;
+        for (int i = i0; i < i1; ++i) {
+            g.v[i - i0] = a.v[i];
+            g.blk0[i - i0] = (int)tot;
+            tot += ((long long)a.v[i].H * a.v[i].W + WTA_PPB * WTA_G - 1) / (WTA_PPB * WTA_G);
+        }
+        g.n = i1 - i0;
+        for (int i = g.n; i <= STAGE_MAXV; ++i) g.blk0[i] = (int)tot;
+        if (tot > 0x7FFFFFFFLL) return fail(SF_EINVAL, "launch_wta_slabs: grid too large");
+        if (tot > 0) {
+            ProfScope prof(mode == WM_RIGHT ? "wta_slab_right" : "wta_slab_left", st);
+            switch (K) {
+            case 2: launch_wta_slab_mode<2>(mode, (unsigned)tot, g, st); break;
+            case 4: launch_wta_slab_mode<4>(mode, (unsigned)tot, g, st); break;
+            case 6: launch_wta_slab_mode<6>(mode, (unsigned)tot, g, st); break;
+            case 8: launch_wta_slab_mode<8>(mode, (unsigned)tot, g, st); break;
+            case 10: launch_wta_slab_mode<10>(mode, (unsigned)tot, g, st); break;
+            case 12: launch_wta_slab_mode<12>(mode, (unsigned)tot, g, st); break;
+            case 14: launch_wta_slab_mode<14>(mode, (unsigned)tot, g, st); break;
+            default: launch_wta_slab_mode<16>(mode, (unsigned)tot, g, st); break;
+            }
+            const int rc = launch_status("wta_slab_kernel");
+            if (rc) return rc;
+        }
+        for (int i = 0; i <= STAGE_MAXV; ++i) a.blk0[i] = g.blk0[i];
+        i0 = i1;
     }
-    return launch_status("wta_slab_kernel");
+    return SF_OK;
 }
 
 int launch_wta_diag_slabs(WtaArgs &a, hipStream_t st)
