@@ -33,7 +33,8 @@ struct CostArgs {
     int vec;  // store width in bytes (16, 4 or 1), set by launch_cost from D and the pointers' alignment
 };
 
-// WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8).
+// WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8;
+// launch_wta_slabs needs nslab = 8, the diagonal-search launch takes 1..8).
 // right_only: write d* to wta only.  Otherwise d*, sub-pixel disparity, the LR
 // check against wta_r (NULL: no check, valid := 1) and optional features.
 // dense: disp holds the sub-pixel disparity everywhere (valid still written).
@@ -53,13 +54,13 @@ struct WtaView {
 
 struct WtaArgs {
     WtaView v[STAGE_MAXV];
-    int blk0[STAGE_MAXV + 1];  // first block of each view; blk0[n] = grid size
+    int blk0[STAGE_MAXV + 1];  // first block of each view; blk0[n] = grid size (set by the launchers)
     int n;
 };
 
 int launch_census(const CensusArgs &a, hipStream_t st);
 int launch_cost(const CostArgs &a, hipStream_t st);
-int launch_wta_slabs(WtaArgs &a, hipStream_t st);       // fills blk0
+int launch_wta_slabs(const WtaArgs &a, hipStream_t st);  // computes the block offsets itself
 int launch_wta_diag_slabs(WtaArgs &a, hipStream_t st);  // fills blk0; W <= 4096
 // out = 3x3 median of dense (clamp-to-edge), or -1 where mask is 0 (mask may be NULL).
 int launch_median_mask(const float *dense, const uint8_t *mask, int H, int W, float *out,

@@ -249,6 +249,10 @@ static int wta_mode(const WtaView &v)
     return v.wta_r ? WM_LR : WM_LEFT;
 }
 
+// The slab WTA sums all eight direction slabs (a compile-time count, so no
+// slab needs masking).
+constexpr int WTA_NSLAB = 8;
+
 // Result of one pixel's reduction, the same in every lane of its group.
 struct WtaPx {
     int ds;                     // d*
@@ -261,7 +265,7 @@ __device__ __forceinline__ WtaPx wta_reduce(const WtaView &v, const u32x2 (&w)[2
     constexpr int D = 16 * K;
     uint32_t sv[2][4];
     int dd[2][8];
-    slab_add<K>(w, j, v.nslab, sv, dd);
+    slab_add<K>(w, j, WTA_NSLAB, sv, dd);
     uint32_t best = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -279,35 +283,49 @@ __device__ __forceinline__ WtaPx wta_reduce(const WtaView &v, const u32x2 (&w)[2
     return r;
 }
 
-// Stores of one pixel (lane 0): d*, and unless right-only the sub-pixel
-// disparity, the LR check with the right map's value rq at x - d*, and the
-// features (inten: the base image byte at the pixel).
+// Stores of one pixel by the lanes of its group: d* (lane 0), and unless
+// right-only the sub-pixel disparity, the LR check with the right map's value
+// rq at x - d* and the valid flag (lane 0), and the four network features
+// (lanes 4..7, one each; inten: the base image byte at the pixel).  The
+// quotients of lane 0 and lanes 4..7 come from one FP32 division of the
+// whole group, each lane with its own operands (the same operations as one
+// lane doing them in turn).
 template <int K, int MODE>
-__device__ __forceinline__ void wta_finish(const WtaView &v, const WtaPx &r, int px, int x, int rq,
+__device__ __forceinline__ void wta_finish(const WtaView &v, const WtaPx &r, int px, int x, int j, int rq,
                                            uint32_t inten)
 {
     constexpr int D = 16 * K;
     if constexpr (MODE == WM_RIGHT) {
-        v.wta[px] = (int16_t)r.ds;
+        if (j == 0) v.wta[px] = (int16_t)r.ds;
     } else {
-        const float sub = subpixel(r.ds, D, r.av, r.smin, r.cv);
-        int ok = 1;
-        if constexpr (wm_lr(MODE)) {
-            int diff = r.ds - rq;
-            diff = diff < 0 ? -diff : diff;
-            ok = (x - r.ds >= 0) && diff <= v.tol;
-        }
-        if (v.wta) v.wta[px] = (int16_t)r.ds;
-        v.disp[px] = (ok || v.dense) ? sub : -1.0f;
-        v.valid[px] = (uint8_t)ok;
+        // Sub-pixel (lane 0): d* + (a - c) / (2 den) when 0 < d* < D - 1 and den > 0.
+        const int den = (int)r.av - 2 * (int)r.smin + (int)r.cv;
+        const bool para = r.ds > 0 && r.ds < D - 1 && den > 0;
+        float num = (float)((int)r.av - (int)r.cv), dvs = (float)(2 * (den > 0 ? den : 1));
         if constexpr (wm_feat(MODE)) {
             const uint32_t s2 = r.s2 == 0xFFFFFFFFu ? r.smin : r.s2;
-            float4 f;
-            f.x = (float)inten / 255.0f;
-            f.y = D > 1 ? (float)r.ds / (float)(D - 1) : 0.0f;
-            f.z = (float)r.smin / (float)(8 * (SF_CMAX + v.P2));
-            f.w = (float)s2 / (float)(r.smin > 1 ? r.smin : 1u);
-            reinterpret_cast<float4 *>(v.feat)[px] = f;
+            const int f = j - 4;  // feature index of lanes 4..7
+            if (f == 0) { num = (float)inten; dvs = 255.0f; }
+            if (f == 1) { num = (float)r.ds; dvs = (float)(D > 1 ? D - 1 : 1); }
+            if (f == 2) { num = (float)r.smin; dvs = (float)(8 * (SF_CMAX + v.P2)); }
+            if (f == 3) { num = (float)s2; dvs = (float)(r.smin > 1 ? r.smin : 1u); }
+        }
+        const float q = num / dvs;
+        if (j == 0) {
+            const float sub = para ? (float)r.ds + q : (float)r.ds;
+            int ok = 1;
+            if constexpr (wm_lr(MODE)) {
+                int diff = r.ds - rq;
+                diff = diff < 0 ? -diff : diff;
+                ok = (x - r.ds >= 0) && diff <= v.tol;
+            }
+            if (v.wta) v.wta[px] = (int16_t)r.ds;
+            v.disp[px] = (ok || v.dense) ? sub : -1.0f;
+            v.valid[px] = (uint8_t)ok;
+        }
+        if constexpr (wm_feat(MODE)) {
+            const int f = j - 4;
+            if (f >= 0 && f < 4) v.feat[(size_t)px * 4 + f] = (f == 1 && D <= 1) ? 0.0f : q;
         }
     }
 }
@@ -317,7 +335,8 @@ __device__ __forceinline__ void wta_finish(const WtaView &v, const WtaPx &r, int
 // and pixel g's right-map value is loaded before pixel g - 1 is finished, so a
 // wait for it never also waits for the next pixel's slabs (loads complete in
 // issue order).  Past the end of the view the group re-reads its last pixel
-// and stores nothing, so every load is issued on every path.
+// and stores nothing, so every load is issued on every path.  The pixel's row
+// and column advance by WTA_PPB per step without a division.
 template <int K, int MODE>
 __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
 {
@@ -329,43 +348,57 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
     const int npx = v.H * v.W;
     constexpr int D = 16 * K;
     const size_t cells = (size_t)npx * D;
-    if (px0 >= npx) return;  // uniform across the 16-lane group (px0 < npx for all in all but the last block)
+    if (px0 >= npx) return;  // uniform across the 16-lane group
     u32x2 w[2][2][8];
     uint32_t inten[2] = {0u, 0u};
-    auto load_inten = [&](int p) -> uint32_t {
-        const int y = p / v.W, x = p - y * v.W;
-        return v.img[(size_t)y * v.pitch + x];
+    // (y, x) of pixel px0 + g WTA_PPB for the current step g, and of the next one.
+    int cy = px0 / v.W, cx = px0 - cy * v.W;
+    auto step_yx = [&](int &yy, int &xx) {
+        xx += WTA_PPB;
+        while (xx >= v.W) {
+            xx -= v.W;
+            ++yy;
+        }
     };
-    slab_load<K>(v.slab, cells, px0, j, v.nslab, w[0]);
-    if constexpr (wm_feat(MODE)) inten[0] = load_inten(px0);
+    auto load_inten = [&](int yy, int xx) -> uint32_t {
+        if (yy >= v.H) { yy = v.H - 1; xx = v.W - 1; }  // past the end: the last pixel
+        return v.img[(size_t)yy * v.pitch + xx];
+    };
+    slab_load<K>(v.slab, cells, px0, j, WTA_NSLAB, w[0]);
+    if constexpr (wm_feat(MODE)) inten[0] = load_inten(cy, cx);
     WtaPx prev{};
     int prev_px = 0, prev_x = 0, prev_rq = 0;
     uint32_t prev_in = 0u;  // inten of the previous pixel (its slot is reused by the prefetch)
 #pragma unroll
     for (int g = 0; g < WTA_G; ++g) {
         const int px = min(px0 + g * WTA_PPB, npx - 1);
+        int ny = cy, nx = cx;
+        step_yx(ny, nx);
         if (g + 1 < WTA_G) {
             const int pn = min(px0 + (g + 1) * WTA_PPB, npx - 1);
-            slab_load<K>(v.slab, cells, pn, j, v.nslab, w[(g + 1) & 1]);
-            if constexpr (wm_feat(MODE)) inten[(g + 1) & 1] = load_inten(pn);
+            slab_load<K>(v.slab, cells, pn, j, WTA_NSLAB, w[(g + 1) & 1]);
+            if constexpr (wm_feat(MODE)) inten[(g + 1) & 1] = load_inten(ny, nx);
             // Keep these loads ahead of pixel g's reduction (the scheduler would
             // otherwise sink them below its waits).
             __builtin_amdgcn_sched_barrier(0);
         }
         const WtaPx r = wta_reduce<K, MODE>(v, w[g & 1], j);
-        const int y = px / v.W, x = px - y * v.W;
+        const bool live = px0 + g * WTA_PPB < npx;
+        const int y = live ? cy : v.H - 1, x = live ? cx : v.W - 1;
         int rq = 0;
         if constexpr (wm_lr(MODE)) rq = v.wta_r[(size_t)y * v.W + max(x - r.ds, 0)];
-        if (g > 0 && j == 0 && px0 + (g - 1) * WTA_PPB < npx)
-            wta_finish<K, MODE>(v, prev, prev_px, prev_x, prev_rq, prev_in);
+        if (g > 0 && px0 + (g - 1) * WTA_PPB < npx)
+            wta_finish<K, MODE>(v, prev, prev_px, prev_x, j, prev_rq, prev_in);
         prev = r;
         prev_px = px;
         prev_x = x;
         prev_rq = rq;
         prev_in = inten[g & 1];
+        cy = ny;
+        cx = nx;
     }
-    if (j == 0 && px0 + (WTA_G - 1) * WTA_PPB < npx)
-        wta_finish<K, MODE>(v, prev, prev_px, prev_x, prev_rq, prev_in);
+    if (px0 + (WTA_G - 1) * WTA_PPB < npx)
+        wta_finish<K, MODE>(v, prev, prev_px, prev_x, j, prev_rq, prev_in);
 }
 
 // Left WTA and the right map by diagonal search in one pass over the left
@@ -451,12 +484,13 @@ static void launch_wta_slab_mode(int mode, unsigned nblk, const WtaArgs &a, hipS
 }
 
 // One launch per run of consecutive views with the same mode (in practice all
-// views of a call share it).  Fills a.blk0 for the last launch's views.
-int launch_wta_slabs(WtaArgs &a, hipStream_t st)
+// views of a call share it); the block offsets of each launch are computed
+// here (a.blk0 is not read).
+int launch_wta_slabs(const WtaArgs &a, hipStream_t st)
 {
     for (int i = 0; i < a.n; ++i) {
         if (a.v[i].D != a.v[0].D) return fail(SF_EINVAL, "launch_wta_slabs: views of one launch need one D");
-        if (a.v[i].nslab < 1 || a.v[i].nslab > 8) return fail(SF_EINVAL, "launch_wta_slabs: nslab must be in [1, 8]");
+        if (a.v[i].nslab != WTA_NSLAB) return fail(SF_EINVAL, "launch_wta_slabs: the slab WTA sums all 8 slabs");
         if (a.v[i].feat && !a.v[i].img) return fail(SF_EINVAL, "launch_wta_slabs: features need the base image");
     }
     const int K = a.v[0].D / 16;
@@ -491,7 +525,6 @@ int launch_wta_slabs(WtaArgs &a, hipStream_t st)
             const int rc = launch_status("wta_slab_kernel");
             if (rc) return rc;
         }
-        for (int i = 0; i <= STAGE_MAXV; ++i) a.blk0[i] = g.blk0[i];
         i0 = i1;
     }
     return SF_OK;
