@@ -6,6 +6,11 @@
 // One 16-lane DPP row per pixel: lane j reads disparities [4c, 4c+4) for
 // c = j, j+16, ... (128 contiguous bytes per row per load), the (S, d) minimum
 // is a row butterfly on the key S * 512 + d, so ties go to the smallest d.
+// The frame and batch paths never write S: wta_slab_kernel sums the eight u8
+// direction slabs of a pixel on the fly (one compile-time mode per launch:
+// right map, left map with or without the LR check, with or without the
+// network features), and wta_diag_slab_kernel adds the diagonal-search right
+// map.
 #include "sf_internal.hpp"
 #include "stages.hpp"
 
