@@ -45,10 +45,11 @@ SWEEP_FRAMES = 2   # frames per tuning in --tuning-sweep; the counters of the la
 
 
 def tuning_candidates():
-    """The 36 aggregation tunings (chains_per_block, prefetch, order,
-    persistent_per_cu) in the order sf_frame_autotune tries them."""
-    return [(cpb, pf, order, pp) for cpb in (4, 8, 16) for order in (0, 1) for pf in (4, 8)
-            for pp in (0, 4, 8)]
+    """The 72 aggregation tunings (chains_per_block, prefetch, order,
+    persistent_per_cu, packed) in the order sf_frame_autotune tries them at
+    D = 128 (packed costs are a candidate where D is 128 or 256)."""
+    return [(cpb, pf, order, pp, pk) for pk in (0, 1) for cpb in (4, 8, 16) for order in (0, 1)
+            for pf in (4, 8) for pp in (0, 4, 8)]
 
 
 def _sources_sha256():
@@ -63,7 +64,7 @@ def _sources_sha256():
 
 def measured_traffic(kernel, tuning):
     """HBM-side bytes per launch of the aggregation kernel under this tuning
-    (a (chains_per_block, prefetch, order, persistent_per_cu) tuple) from the
+    (a (chains_per_block, prefetch, order, persistent_per_cu, packed) tuple) from the
     committed counter table, only if the kernel sources are unchanged since the
     counters were taken; None otherwise."""
     if not kernel.startswith("sgm_tasks") or not os.path.exists(TRAFFIC_JSON):
@@ -121,7 +122,7 @@ def write_traffic_table(fetch_db, write_db, out=TRAFFIC_JSON):
     rec = {"kernels": names,
            "workload": "plain scene-flow frame 1242x375 D=128, all 4 views in one aggregation launch; "
                        f"{SWEEP_FRAMES} frames per tuning, counters of the last one",
-           "keys": "chains_per_block,prefetch,order,persistent_per_cu",
+           "keys": "chains_per_block,prefetch,order,persistent_per_cu,packed",
            "sources": TRAFFIC_SOURCES, "sources_sha256": _sources_sha256(),
            "copy_calibration": {"bytes": 1 << 30, "fetch_size_kib": cf, "write_size_kib": cw,
                                 "fetch_factor": ff, "write_factor": fw},
@@ -835,9 +836,10 @@ def main():
     torch.cuda.synchronize()
     # The tuning the fused plan runs (the plan's default when none is given).
     if tuning is not None:
-        tuning_key = (tuning.chains_per_block, tuning.prefetch, tuning.order, tuning.persistent_per_cu)
+        tuning_key = (tuning.chains_per_block, tuning.prefetch, tuning.order, tuning.persistent_per_cu,
+                      tuning.packed)
     else:
-        tuning_key = (16, 8, 0, 8 if args.pipeline == "persistent" else 0)
+        tuning_key = (16, 8, 0, 8 if args.pipeline == "persistent" else 0, 0)
 
     # Dominant kernel: the path aggregation (one launch for all 4 views, or one per view).
     kname, views_per_launch = ("sgm_paths", 1) if args.pipeline == "stages" else ("sgm_tasks", 4)

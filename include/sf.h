@@ -204,9 +204,14 @@ typedef struct sf_plan_s *sf_plan;
  *   order             0 = tasks longest chains first, 1 = view by view
  *   persistent_per_cu 0 = one block per task; k > 0 = k blocks per CU pulling
  *                     tasks from a counter
+ *   packed            0 = the run's internal cost volumes hold one byte per
+ *                     cost; 1 = 6-bit costs, 0.75 D bytes per pixel, where D
+ *                     is 128 or 256 (otherwise bytes): a quarter fewer bytes
+ *                     written by the cost stage and re-read by each of the
+ *                     eight directions, for a few more instructions per step
  * Every tuning gives identical results. */
 typedef struct {
-    int chains_per_block, prefetch, order, persistent_per_cu;
+    int chains_per_block, prefetch, order, persistent_per_cu, packed;
 } sf_agg_tuning;
 size_t sf_plan_workspace_bytes(sf_plan plan);
 int sf_plan_destroy(sf_plan plan);
@@ -251,8 +256,9 @@ int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, const uint8
 /* Frame autotuner: times whole frames (sf_frame_run, or sf_frame_run_learned
  * with zero network parameters) of a plan with the given size, penalties and
  * flags for every candidate aggregation tuning (chains per block x prefetch x
- * order x persistence), on seeded synthetic images, and returns the tuning with
- * the fastest median frame and that time in ms.  In a frame the aggregation
+ * order x persistence x packed costs where D allows), on seeded synthetic
+ * images, and returns the tuning with the fastest median frame and that time
+ * in ms.  In a frame the aggregation
  * shares the memory system with the cost and WTA stages, so this choice can
  * differ from sf_agg_autotune's.  Allocates and frees its own buffers;
  * synchronises the stream.  Errors: those of sf_frame_plan_create, SF_EINVAL
@@ -281,7 +287,7 @@ int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, con
  * device task table.  Device pointers in the pair descriptors are fixed at plan
  * creation and must stay valid while the plan is used.
  * Tuning of the aggregation per size class (sf_agg_tuning; classes numbered in
- * order of first appearance in `pairs`; NULL / missing = {16, 8, 0, 0}).
+ * order of first appearance in `pairs`; NULL / missing = {16, 8, 0, 0, 0}).
  * Supported: D a multiple of 32 in [32, 256]; 62 + P2 <= 255; H * W * D < 2^31 per pair.
  * Errors: SF_EINVAL, SF_EUNSUPPORTED, SF_EHIP (table upload). */
 typedef struct {
@@ -303,9 +309,9 @@ int sf_batch_run(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
 int sf_batch_capture(sf_plan plan, void *workspace, size_t ws_bytes, void *stream);
 int sf_batch_launch(sf_plan plan, void *stream);
 /* Autotuner: times every candidate tuning (chains per block x prefetch x order x
- * persistence) of one aggregation launch over nviews views of H x W x D
- * (synthetic costs; 2 = a stereo pair, 4 = a scene-flow frame) on `stream`, and
- * returns the fastest and its median time over five runs, each started right
+ * persistence x packed costs where D allows) of one aggregation launch over
+ * nviews views of H x W x D (synthetic costs; 2 = a stereo pair, 4 = a
+ * scene-flow frame) on `stream`, and returns the fastest and its median time over five runs, each started right
  * after the cost volumes were rewritten (as in a frame, where the cost stage
  * precedes the aggregation).  Allocates and frees its own scratch;
  * synchronises the stream. */

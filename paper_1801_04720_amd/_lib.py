@@ -34,7 +34,7 @@ class SfPair(ct.Structure):
 
 class SfAggTuning(ct.Structure):
     _fields_ = [("chains_per_block", ct.c_int), ("prefetch", ct.c_int), ("order", ct.c_int),
-                ("persistent_per_cu", ct.c_int)]
+                ("persistent_per_cu", ct.c_int), ("packed", ct.c_int)]
 
 
 class SfError(RuntimeError):

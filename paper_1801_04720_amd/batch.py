@@ -27,7 +27,12 @@ def _arch() -> str:
 
 def tuning_dict(t: SfAggTuning) -> dict:
     return {"chains_per_block": t.chains_per_block, "prefetch": t.prefetch, "order": t.order,
-            "persistent_per_cu": t.persistent_per_cu}
+            "persistent_per_cu": t.persistent_per_cu, "packed": t.packed}
+
+
+def _from_cache(e: dict) -> SfAggTuning:
+    return SfAggTuning(e["chains_per_block"], e["prefetch"], e["order"], e["persistent_per_cu"],
+                       e.get("packed", 0))
 
 
 def autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, cache: str | None = DEFAULT_CACHE,
@@ -41,7 +46,7 @@ def autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, cache: str | N
             db = json.load(f)
     if key in db and not refresh:
         e = db[key]
-        return SfAggTuning(e["chains_per_block"], e["prefetch"], e["order"], e["persistent_per_cu"]), e.get("ms")
+        return _from_cache(e), e.get("ms")
     best = SfAggTuning()
     ms = ct.c_float(0.0)
     check(lib().sf_agg_autotune(H, W, D, P1, P2, nviews, _stream(stream), ct.byref(best), ct.byref(ms)))
@@ -67,7 +72,7 @@ def frame_autotune(H: int, W: int, D: int, P1: int = 10, P2: int = 120, lr_tol: 
             db = json.load(f)
     if key in db and not refresh:
         e = db[key]
-        return SfAggTuning(e["chains_per_block"], e["prefetch"], e["order"], e["persistent_per_cu"]), e.get("ms")
+        return _from_cache(e), e.get("ms")
     best = SfAggTuning()
     ms = ct.c_float(0.0)
     check(lib().sf_frame_autotune(H, W, D, P1, P2, lr_tol, flags, _stream(stream), ct.byref(best), ct.byref(ms)))
@@ -111,7 +116,7 @@ class Batch:
             tun = (SfAggTuning * len(classes))()
             for c, k in enumerate(classes):
                 t = tunings.get(k) if isinstance(tunings, dict) else tunings[c]
-                tun[c] = t if t is not None else SfAggTuning(16, 8, 0, 0)
+                tun[c] = t if t is not None else SfAggTuning(16, 8, 0, 0, 0)
             ntun = len(classes)
         h = ct.c_void_p()
         check(lib().sf_batch_plan_create(arr, len(pairs), P1, P2, lr_tol, tun, ntun, mem_budget,

@@ -91,6 +91,7 @@ static int check_tuning(const sf_agg_tuning &t)
     if (t.order != 0 && t.order != 1) return fail(SF_EINVAL, "tuning: order must be 0 or 1");
     if (t.persistent_per_cu < 0 || t.persistent_per_cu > 32)
         return fail(SF_EINVAL, "tuning: persistent_per_cu must be in [0, 32]");
+    if (t.packed != 0 && t.packed != 1) return fail(SF_EINVAL, "tuning: packed must be 0 or 1");
     return SF_OK;
 }
 
@@ -100,6 +101,14 @@ static int cu_count()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     return ncu;
+}
+
+// As in the frame: 6-bit packed costs when the class's tuning asks for them,
+// D = 128 or 256, and the workspace keeps the cost volumes (256-byte offsets)
+// 4-byte aligned.
+static bool batch_packed(int packed, int D, const void *ws)
+{
+    return packed && cost_packable(D) && (reinterpret_cast<uintptr_t>(ws) & 3) == 0;
 }
 
 static int batch_enqueue(Plan *p, uint8_t *ws, hipStream_t st)
@@ -136,6 +145,7 @@ static int batch_enqueue(Plan *p, uint8_t *ws, hipStream_t st)
                 ca.H = co.H = H;
                 ca.W = co.W = W;
                 co.D = D;
+                co.packed = batch_packed(B.tuning[g.cls].packed, D, ws);
                 if ((rc = launch_census(ca, st))) return rc;
                 if ((rc = launch_cost(co, st))) return rc;
             }
@@ -148,7 +158,8 @@ static int batch_enqueue(Plan *p, uint8_t *ws, hipStream_t st)
             if ((rc = launch_agg_tasks(reinterpret_cast<AggView *>(tab + g.views_off),
                                        reinterpret_cast<AggTask *>(tab + g.tasks_off), g.ntasks,
                                        D / 16, ws, reinterpret_cast<int *>(tab + g.counter_off),
-                                       t.persistent_per_cu * ncu, st, t.chains_per_block, t.prefetch)))
+                                       t.persistent_per_cu * ncu, st, t.chains_per_block, t.prefetch,
+                                       nullptr, batch_packed(t.packed, D, ws))))
                 return rc;
         }
         // WTA of the right views, then WTA + LR check of the left views.
@@ -241,7 +252,7 @@ extern "C" int sf_batch_plan_create(const sf_pair *pairs, int n, int P1, int P2,
         pair_cls[i] = it->second;
     }
     const int ncls = (int)B->classes.size();
-    B->tuning.assign(ncls, sf_agg_tuning{16, 8, 0, 0});
+    B->tuning.assign(ncls, sf_agg_tuning{16, 8, 0, 0, 0});
     for (int c = 0; c < ncls && tunings && c < ntunings; ++c) {
         int rc = check_tuning(tunings[c]);
         if (rc) {
@@ -443,12 +454,13 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
             hipMemcpy(tab + bv, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice);
             hipMemset(tab + bv + bt, 0, sizeof(int));  // the persistent counter starts at 0
             for (int pf : prefs)
-                for (int pp : pers) {
+                for (int pp : pers)
+                    for (int pk = 0; pk <= (cost_packable(D) ? 1 : 0) && rc == SF_OK; ++pk) {
                     auto go = [&]() {
                         return launch_agg_tasks(reinterpret_cast<AggView *>(tab),
                                                 reinterpret_cast<AggTask *>(tab + bv), (int)tasks.size(),
                                                 D / 16, ws, reinterpret_cast<int *>(tab + bv + bt), pp * ncu,
-                                                st, cpb, pf);
+                                                st, cpb, pf, nullptr, batch_packed(pk, D, ws));
                     };
                     if ((rc = go())) break;
                     float tms[5];
@@ -468,7 +480,7 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
                     std::sort(tms, tms + 5);
                     if (tms[2] < best_t) {
                         best_t = tms[2];
-                        *best = sf_agg_tuning{cpb, pf, order, pp};
+                        *best = sf_agg_tuning{cpb, pf, order, pp, pk};
                     }
                 }
             hipFree(tab);

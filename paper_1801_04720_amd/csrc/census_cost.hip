@@ -192,7 +192,22 @@ __device__ __forceinline__ uint32_t hamming(uint64_t b, uint64_t m)
     return (uint32_t)__popc((uint32_t)x) + (uint32_t)__popc((uint32_t)(x >> 32));
 }
 
-template <bool RIGHT, bool EDGE>
+// 16 six-bit values (LSB first) packed into three dwords.
+__device__ __forceinline__ uint3 pack6x16(const uint32_t (&v)[16])
+{
+    uint32_t p[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int bit = 6 * e, w = bit >> 5, s = bit & 31;
+        p[w] |= v[e] << s;
+        if (s > 26) p[w + 1] |= v[e] >> (32 - s);  // the field crosses into the next dword
+    }
+    return make_uint3(p[0], p[1], p[2]);
+}
+
+// PACK: write the 16 costs of the run as 6-bit fields (12 bytes at byte 12c of
+// the pixel's 0.75 D bytes); otherwise as 16 bytes at byte 16c of its D bytes.
+template <bool RIGHT, bool EDGE, bool PACK = false>
 __device__ __forceinline__ void cost_run16(const uint64_t *sb, const uint64_t *sm, int j, int c,
                                            int x0, int W, int D, uint8_t *row)
 {
@@ -208,24 +223,26 @@ __device__ __forceinline__ void cost_run16(const uint64_t *sb, const uint64_t *s
         const int xl = j * CV_R + r;  // block-local pixel
         const int x = x0 + xl;
         const uint64_t b = sb[cv_swz(xl)];
-        uint32_t w[4];
+        uint32_t v[16];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t acc = 0;
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                const int e = 4 * q + e4;
-                uint32_t v = hamming(b, win[RIGHT ? r + e : r - e + 15]);
-                if (EDGE) {
-                    const int d = 16 * c + e;
-                    const bool out = RIGHT ? (x + d >= W) : (x - d < 0);
-                    v = out ? (uint32_t)SF_CMAX : v;
-                }
-                acc = e4 == 0 ? v : (acc | (v << (8 * e4)));
+        for (int e = 0; e < 16; ++e) {
+            v[e] = hamming(b, win[RIGHT ? r + e : r - e + 15]);
+            if (EDGE) {
+                const int d = 16 * c + e;
+                const bool out = RIGHT ? (x + d >= W) : (x - d < 0);
+                v[e] = out ? (uint32_t)SF_CMAX : v[e];
             }
-            w[q] = acc;
         }
-        if (x < W) reinterpret_cast<uint4 *>(row + (size_t)xl * D)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+        if (x >= W) continue;
+        if constexpr (PACK) {
+            *reinterpret_cast<uint3 *>(row + (size_t)xl * (3 * D / 4) + 12 * c) = pack6x16(v);
+        } else {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                w[q] = v[4 * q] | (v[4 * q + 1] << 8) | (v[4 * q + 2] << 16) | (v[4 * q + 3] << 24);
+            reinterpret_cast<uint4 *>(row + (size_t)xl * D)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
     }
 }
 
@@ -259,17 +276,23 @@ __global__ __launch_bounds__(CV_NT) void cost16_kernel(CostArgs a)
     const int t = threadIdx.x;
     const int c = t % cpp, j = t / cpp;
     if (j >= runs) return;
-    uint8_t *row = a.cost[blockIdx.z] + ((size_t)y * W + x0) * D;
-    if (RIGHT) {
-        if (x0 + TP + D - 2 >= W)
-            cost_run16<true, true>(sb, sm, j, c, x0, W, D, row);
+    const bool edge = RIGHT ? (x0 + TP + D - 2 >= W) : (x0 < D - 1);
+    if (a.packed) {
+        uint8_t *row = a.cost[blockIdx.z] + ((size_t)y * W + x0) * (3 * D / 4);
+        if (RIGHT)
+            edge ? cost_run16<true, true, true>(sb, sm, j, c, x0, W, D, row)
+                 : cost_run16<true, false, true>(sb, sm, j, c, x0, W, D, row);
         else
-            cost_run16<true, false>(sb, sm, j, c, x0, W, D, row);
+            edge ? cost_run16<false, true, true>(sb, sm, j, c, x0, W, D, row)
+                 : cost_run16<false, false, true>(sb, sm, j, c, x0, W, D, row);
     } else {
-        if (x0 < D - 1)
-            cost_run16<false, true>(sb, sm, j, c, x0, W, D, row);
+        uint8_t *row = a.cost[blockIdx.z] + ((size_t)y * W + x0) * D;
+        if (RIGHT)
+            edge ? cost_run16<true, true>(sb, sm, j, c, x0, W, D, row)
+                 : cost_run16<true, false>(sb, sm, j, c, x0, W, D, row);
         else
-            cost_run16<false, false>(sb, sm, j, c, x0, W, D, row);
+            edge ? cost_run16<false, true>(sb, sm, j, c, x0, W, D, row)
+                 : cost_run16<false, false>(sb, sm, j, c, x0, W, D, row);
     }
 }
 
@@ -296,6 +319,11 @@ int launch_cost(const CostArgs &args, hipStream_t st)
     uintptr_t ptr_bits = 0;
     for (int i = 0; i < a.n; ++i) ptr_bits |= reinterpret_cast<uintptr_t>(a.cost[i]);
     a.vec = ((a.D & 15) == 0 && (ptr_bits & 15) == 0) ? 16 : ((a.D & 3) == 0 && (ptr_bits & 3) == 0) ? 4 : 1;
+    if (a.packed) {
+        if (!cost_packable(a.D) || (ptr_bits & 3) != 0)
+            return fail(SF_EINVAL, "launch_cost: packed costs need D = 128 or 256 and 4-byte aligned volumes");
+        a.vec = 16;  // the 16-disparity-run kernel writes the packed runs
+    }
     ProfScope prof("cost", st);
     if (a.vec == 16) {
         const int TP = cv_tile(a.D);

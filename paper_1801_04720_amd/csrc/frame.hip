@@ -22,6 +22,15 @@ namespace sf {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Whether a run aggregates from 6-bit packed costs: the tuning asks for them,
+// D = 128 or 256, and the workspace keeps the cost volumes (at 256-byte
+// offsets) 4-byte aligned.  The cost and aggregation launches of a run take
+// the same answer.
+static bool frame_packed(const sf_agg_tuning &t, int D, const void *ws)
+{
+    return t.packed && cost_packable(D) && (reinterpret_cast<uintptr_t>(ws) & 3) == 0;
+}
+
 int plan_upload_tables(Plan &p, const std::vector<AggView> &views, const std::vector<AggTask> &tasks)
 {
     p.ntasks = (int)tasks.size();
@@ -75,7 +84,7 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
                "sf_frame_plan_create: SF_FRAME_DIAG and SF_FRAME_LEARNED exclude each other");
     SF_REQUIRE(!(flags & SF_FRAME_DIAG) || W <= 4096, SF_EUNSUPPORTED,
                "sf_frame_plan_create: SF_FRAME_DIAG needs W <= 4096");
-    sf_agg_tuning tun{16, 8, 0, (flags & SF_FRAME_PERSISTENT) ? 8 : 0};
+    sf_agg_tuning tun{16, 8, 0, (flags & SF_FRAME_PERSISTENT) ? 8 : 0, 0};
     if (tuning) {
         tun = *tuning;
         SF_REQUIRE(tun.chains_per_block == 4 || tun.chains_per_block == 8 || tun.chains_per_block == 16,
@@ -85,6 +94,7 @@ extern "C" int sf_frame_plan_create(int H, int W, int D, int P1, int P2, int lr_
         SF_REQUIRE(tun.order == 0 || tun.order == 1, SF_EINVAL, "sf_frame_plan_create: order must be 0 or 1");
         SF_REQUIRE(tun.persistent_per_cu >= 0 && tun.persistent_per_cu <= 32, SF_EINVAL,
                    "sf_frame_plan_create: persistent_per_cu must be in [0, 32]");
+        SF_REQUIRE(tun.packed == 0 || tun.packed == 1, SF_EINVAL, "sf_frame_plan_create: packed must be 0 or 1");
     }
     Plan *p = new (std::nothrow) Plan();
     if (!p) return fail(SF_ENOMEM, "sf_frame_plan_create: out of host memory");
@@ -183,6 +193,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
     uint8_t *ws = static_cast<uint8_t *>(workspace);
     const int H = p->H, W = p->W, D = p->D;
     auto at = [&](size_t off) { return ws + off; };
+    const bool packed = frame_packed(p->tuning, D, ws);
     const uint8_t *img[4] = {L0, R0, L1, R1};
     uint64_t *cen[4];
     for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
@@ -216,6 +227,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
             co.cost[t] = at(p->off_cost[t]);
         }
         co.n = 2; co.H = H; co.W = W; co.D = D;
+        co.packed = packed;
         if ((rc = launch_cost(co, st))) return rc;
         AggImages ims{};
         if (p->adaptive) {
@@ -224,7 +236,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
         }
         if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
                                    p->persistent_blocks, st, p->tuning.chains_per_block,
-                                   p->tuning.prefetch, &ims)))
+                                   p->tuning.prefetch, &ims, packed)))
             return rc;
         WtaArgs wd{};
         for (int t = 0; t < 2; ++t) {
@@ -248,6 +260,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
         }
         for (int i = 0; i < 4; ++i) co.cost[i] = at(p->off_cost[i]);
         co.n = 4; co.H = H; co.W = W; co.D = D;
+        co.packed = packed;
         if ((rc = launch_cost(co, st))) return rc;
 
         // Each view's base image: L0, R0, L1, R1.
@@ -258,7 +271,7 @@ extern "C" int sf_frame_run(sf_plan plan, const uint8_t *L0, const uint8_t *R0, 
         }
         if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
                                    p->persistent_blocks, st, p->tuning.chains_per_block,
-                                   p->tuning.prefetch, &ims)))
+                                   p->tuning.prefetch, &ims, packed)))
             return rc;
 
         WtaArgs wr{};
@@ -319,6 +332,7 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     uint8_t *ws = static_cast<uint8_t *>(workspace);
     const int H = p->H, W = p->W, D = p->D;
     auto at = [&](size_t off) { return ws + off; };
+    const bool packed = frame_packed(p->tuning, D, ws);
     const uint8_t *img[4] = {L0, R0, L1, R1};
     uint64_t *cen[4];
     for (int i = 0; i < 4; ++i) cen[i] = reinterpret_cast<uint64_t *>(at(p->off_cen[i]));
@@ -339,6 +353,7 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
         co.cost[t] = at(p->off_cost[t]);
     }
     co.n = 2; co.H = H; co.W = W; co.D = D;
+    co.packed = packed;
     if ((rc = launch_cost(co, st))) return rc;
     AggImages ims{};
     if (p->adaptive) {
@@ -347,7 +362,7 @@ extern "C" int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8
     }
     if ((rc = launch_agg_tasks(p->d_views, p->d_tasks, p->ntasks, D / 16, ws, p->d_counter,
                                p->persistent_blocks, st, p->tuning.chains_per_block,
-                               p->tuning.prefetch, &ims)))
+                               p->tuning.prefetch, &ims, packed)))
         return rc;
     // WTA + sub-pixel + features of both left maps (no right view).
     float *feat = reinterpret_cast<float *>(at(p->off_feat));
@@ -457,12 +472,14 @@ extern "C" int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best_t = 1e30f;
-    // Candidates: chains per block x order x prefetch x persistent blocks per CU.
+    // Candidates: packed costs (where D allows) x chains per block x order x prefetch x
+    // persistent blocks per CU.
     std::vector<sf_agg_tuning> cand;
-    for (int cpb : {4, 8, 16})
-        for (int order : {0, 1})
-            for (int pf : {4, 8})
-                for (int pp : {0, 4, 8}) cand.push_back(sf_agg_tuning{cpb, pf, order, pp});
+    for (int pk = 0; pk <= (cost_packable(D) ? 1 : 0); ++pk)
+        for (int cpb : {4, 8, 16})
+            for (int order : {0, 1})
+                for (int pf : {4, 8})
+                    for (int pp : {0, 4, 8}) cand.push_back(sf_agg_tuning{cpb, pf, order, pp, pk});
     constexpr int REPS = 5, FRAMES = 3;
     for (size_t c = 0; c < cand.size() && rc == SF_OK; ++c) {
         sf_plan pl = nullptr;

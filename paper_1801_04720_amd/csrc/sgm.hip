@@ -34,6 +34,8 @@
 //     of uneven stereo pairs) from a task table sorted longest chains first,
 //     each block one task of up to 16 chains of one view and direction, K
 //     chosen per task; optionally persistent, pulling tasks from a counter.
+#include <type_traits>
+
 #include "sf_internal.hpp"
 #include "sgm_tasks.hpp"
 
@@ -250,13 +252,72 @@ __device__ __forceinline__ void emit_buf(const uint32_t (&L)[K / 2], __amdgpu_bu
     }
 }
 
+// Packed costs (6 bits each, the frame and batch paths at D = 128 or 256):
+// lane j's K costs d = jK .. jK + K - 1 are K consecutive 6-bit fields.  For
+// K = 8 they are the 6 bytes at byte 6j of the pixel's 96; the lane reads the
+// 8 aligned bytes at 12 (j / 2) + 4 (j % 2) and drops 16 bits when j is odd.
+// For K = 16 they are the 12 bytes at byte 12j of the pixel's 192.
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+
+template <int K>
+struct CostPk {
+    static_assert(K == 8 || K == 16, "packed costs need K = 8 or 16");
+    uint32_t w[K == 8 ? 2 : 3];
+};
+
+template <int K>
+__device__ __forceinline__ uint32_t pk_lane_off(int j)
+{
+    return K == 8 ? (uint32_t)(12 * (j >> 1) + 4 * (j & 1)) : (uint32_t)(12 * j);
+}
+
+template <int K>
+__device__ __forceinline__ void load_pk_buf(__amdgpu_buffer_rsrc_t rs, uint32_t off, CostPk<K> &r)
+{
+    if constexpr (K == 8) {
+        const u32x2 v = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0));
+        r.w[0] = v.x;
+        r.w[1] = v.y;
+    } else {
+        const u32x3 v = __builtin_bit_cast(u32x3, __builtin_amdgcn_raw_buffer_load_b96(rs, (int)off, 0, 0));
+        r.w[0] = v.x;
+        r.w[1] = v.y;
+        r.w[2] = v.z;
+    }
+}
+
+// Field e (bits 6e .. 6e + 5) of a little-endian multiword (e a constant).
+template <int NW>
+__device__ __forceinline__ uint32_t field6(const uint32_t (&w)[NW], int e)
+{
+    const int bit = 6 * e, k = bit >> 5, s = bit & 31;
+    if (s <= 26) return (w[k] >> s) & 63u;
+    return __builtin_amdgcn_alignbit(w[k + 1], w[k], s) & 63u;
+}
+
+// Packed costs -> interleaved u16 pairs: pair i = (d = jK + i, d = jK + K/2 + i).
+template <int K>
+__device__ __forceinline__ void unpack_pk(const CostPk<K> &r, int j, uint32_t (&c)[K / 2])
+{
+    if constexpr (K == 8) {
+        const uint32_t sh = 16u * (uint32_t)(j & 1);
+        const uint32_t f[2] = {__builtin_amdgcn_alignbit(r.w[1], r.w[0], sh), r.w[1] >> sh};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c[i] = field6<2>(f, i) | (field6<2>(f, i + 4) << 16);
+    } else {
+        (void)j;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) c[i] = field6<3>(r.w, i) | (field6<3>(r.w, i + 8) << 16);
+    }
+}
+
 // Default prefetch depth (steps) of the cost stream of one chain.
 constexpr int SGM_U = 8;
 
 // Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
 // cost: [H][W][D]; slab: this direction's [H][W][D] u8 slab (ATOMIC == false)
 // or S [H][W][D] u16 (ATOMIC == true).
-template <int K, bool ATOMIC, int U = SGM_U, bool ADAPT = false>
+template <int K, bool ATOMIC, int U = SGM_U, bool ADAPT = false, bool PACK = false>
 __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
                                           uint16_t *__restrict__ S, int H, int W, int P1, int P2,
                                           int r, int l, int j, const uint8_t *img = nullptr,
@@ -264,16 +325,19 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
 {
     constexpr int D = 16 * K;
     constexpr int NP = K / 2;
+    constexpr int CPX = PACK ? 3 * D / 4 : D;  // cost bytes per pixel
     int x, y, len;
     chain_geometry(r, l, H, W, x, y, len);
     const int rx = c_dir[r][0], ry = c_dir[r][1];
-    // Byte step along the chain in the [H][W][D] volumes.
+    // Byte steps along the chain in the [H][W][D] output volumes and the cost volume.
     const ptrdiff_t bstep = ((ptrdiff_t)ry * W + rx) * D;
     const size_t b0 = ((size_t)y * W + x) * D + (size_t)j * K;
+    const ptrdiff_t cstep = ((ptrdiff_t)ry * W + rx) * CPX;
+    const size_t c0 = ((size_t)y * W + x) * CPX + (PACK ? (size_t)pk_lane_off<PACK ? K : 8>(j) : (size_t)j * K);
     // Cost volume through a buffer resource (the volume is < 2^31 bytes).
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-        const_cast<uint8_t *>(cost), (short)0, (int)((size_t)H * W * D), SGM_RSRC_WORD3);
-    uint32_t ld = (uint32_t)b0;                                  // next cost load (offset)
+        const_cast<uint8_t *>(cost), (short)0, (int)((size_t)H * W * CPX), SGM_RSRC_WORD3);
+    uint32_t ld = (uint32_t)c0;                                  // next cost load (offset)
     const __amdgpu_buffer_rsrc_t rs_out = __builtin_amdgcn_make_buffer_rsrc(
         ATOMIC ? (void *)S : (void *)slab, (short)0, (int)((size_t)H * W * D), SGM_RSRC_WORD3);
     uint32_t st = (uint32_t)b0;                                  // next slab store (offset)
@@ -300,12 +364,16 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     uint32_t below = SGM_SENT, above = SGM_SENT;
     // Steps past the end of this chain (other chains of the wave may be longer)
     // load whatever the buffer holds there (zeros beyond it) and store nothing.
-    auto fetch = [&](int t0, CostRaw<K>(&buf)[U], uint32_t(&ib)[U]) {
+    using Raw = std::conditional_t<PACK, CostPk<PACK ? K : 8>, CostRaw<K>>;
+    auto fetch = [&](int t0, Raw(&buf)[U], uint32_t(&ib)[U]) {
         (void)t0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            load_raw_buf<K>(rs, ld, buf[u]);
-            ld += (uint32_t)bstep;
+            if constexpr (PACK)
+                load_pk_buf<K>(rs, ld, buf[u]);
+            else
+                load_raw_buf<K>(rs, ld, buf[u]);
+            ld += (uint32_t)cstep;
             if constexpr (ADAPT) {
                 ib[u] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs_img, (int)ild, 0, 0);
                 ild += istep;
@@ -314,9 +382,12 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
             }
         }
     };
-    auto step = [&](int t, const CostRaw<K> &raw, uint32_t inten) {
+    auto step = [&](int t, const Raw &raw, uint32_t inten) {
         uint32_t c[NP];
-        unpack<K>(raw, c);
+        if constexpr (PACK)
+            unpack_pk<K>(raw, j, c);
+        else
+            unpack<K>(raw, c);
         below = dpp_fill<DPP_ROW_SHR1>(below, L[NP - 1]);
         above = dpp_fill<DPP_ROW_SHL1>(above, L[0]);
         uint32_t p2 = (uint32_t)P2;
@@ -369,7 +440,7 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
         M = row16_min(min((uint32_t)m2.x, (uint32_t)m2.y));
     };
 
-    CostRaw<K> bufA[U], bufB[U];
+    Raw bufA[U], bufB[U];
     uint32_t ibA[U], ibB[U];
     fetch(0, bufA, ibA);
     for (int t0 = 0; t0 < len; t0 += 2 * U) {
@@ -410,7 +481,7 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
 // and is 0 again when the launch ends: every block pulls exactly one index >=
 // ntasks, on its way out, so the block that pulls ntasks + gridDim.x - 1 makes
 // the launch's last pull and resets it (no clearing launch between frames).
-template <int K, int U, bool ADAPT>
+template <int K, int U, bool ADAPT, bool PACK = false>
 __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__restrict__ views,
                                                            const AggTask *__restrict__ tasks,
                                                            int ntasks, uint8_t *base,
@@ -438,8 +509,8 @@ __global__ __launch_bounds__(SGM_NT) void sgm_tasks_kernel(const AggView *__rest
                             (size_t)tk.slot * v.H * v.W * (16 * K);
             const uint8_t *img = ADAPT ? ims.img[tk.view] : nullptr;
             const int pitch = ADAPT ? ims.pitch[tk.view] : 0;
-            sgm_chain<K, false, U, ADAPT>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
-                                          tk.line0 + q, j, img, pitch);
+            sgm_chain<K, false, U, ADAPT, PACK>(cost, slab, nullptr, v.H, v.W, v.P1, v.P2, v.dir[tk.slot],
+                                                tk.line0 + q, j, img, pitch);
         }
         if (!counter) return;
     }
@@ -558,31 +629,46 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
     tasks.swap(out);
 }
 
-template <int K>
-static void launch_tasks_k(int U, int nb, int nthr, hipStream_t st, const AggView *v,
-                           const AggTask *t, int n, uint8_t *base, int *counter, const AggImages &ims)
+template <int K, bool PACK>
+static void launch_tasks_kp(int U, int nb, int nthr, hipStream_t st, const AggView *v,
+                            const AggTask *t, int n, uint8_t *base, int *counter, const AggImages &ims)
 {
     if (ims.n > 0) {
         if (U == 4)
-            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, true>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, true, PACK>), dim3(nb), dim3(nthr), 0, st, v, t, n,
                                base, counter, ims);
         else
-            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, true>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, true, PACK>), dim3(nb), dim3(nthr), 0, st, v, t, n,
                                base, counter, ims);
     } else {
         if (U == 4)
-            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, false>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 4, false, PACK>), dim3(nb), dim3(nthr), 0, st, v, t, n,
                                base, counter, ims);
         else
-            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, false>), dim3(nb), dim3(nthr), 0, st, v, t, n,
+            hipLaunchKernelGGL((sgm_tasks_kernel<K, 8, false, PACK>), dim3(nb), dim3(nthr), 0, st, v, t, n,
                                base, counter, ims);
     }
 }
 
+template <int K>
+static void launch_tasks_k(int U, int nb, int nthr, hipStream_t st, const AggView *v,
+                           const AggTask *t, int n, uint8_t *base, int *counter, const AggImages &ims,
+                           bool packed)
+{
+    if constexpr (K == 8 || K == 16) {
+        if (packed) {
+            launch_tasks_kp<K, true>(U, nb, nthr, st, v, t, n, base, counter, ims);
+            return;
+        }
+    }
+    launch_tasks_kp<K, false>(U, nb, nthr, st, v, t, n, base, counter, ims);
+}
+
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
                      uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
-                     int chains_per_block, int prefetch, const AggImages *images)
+                     int chains_per_block, int prefetch, const AggImages *images, bool packed)
 {
+    if (packed && K != 8 && K != 16) return fail(SF_EINVAL, "launch_agg_tasks: packed costs need D = 128 or 256");
     AggImages ims{};
     if (images) ims = *images;
     if (ims.n < 0 || ims.n > AGG_MAX_IMG) return fail(SF_EINVAL, "launch_agg_tasks: bad image count");
@@ -602,14 +688,14 @@ int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks,
     ProfScope prof("sgm_tasks", st);  // the aggregation launch alone
     const int nthr = 16 * chains_per_block;
     switch (K) {
-    case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 4: launch_tasks_k<4>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 6: launch_tasks_k<6>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 8: launch_tasks_k<8>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 10: launch_tasks_k<10>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 12: launch_tasks_k<12>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 14: launch_tasks_k<14>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
-    case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims); break;
+    case 2: launch_tasks_k<2>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 4: launch_tasks_k<4>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 6: launch_tasks_k<6>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 8: launch_tasks_k<8>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 10: launch_tasks_k<10>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 12: launch_tasks_k<12>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 14: launch_tasks_k<14>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
+    case 16: launch_tasks_k<16>(prefetch, nb, nthr, st, d_views, d_tasks, ntasks, base, counter, ims, packed); break;
     default: return fail(SF_EUNSUPPORTED, "launch_agg_tasks: unsupported K");
     }
     const int rc = launch_status("sgm_tasks_kernel");

@@ -46,8 +46,10 @@ void sort_tasks_longest_first(std::vector<AggTask> &tasks, const std::vector<int
 // prefetch (cost steps in flight per chain) in {4, 8}.
 // images: NULL or n = 0 for the constant P2; otherwise every view index of the
 // table must be < n.
+// packed: the cost volumes hold 6-bit costs (CostArgs::packed; K = 8 or 16).
 int launch_agg_tasks(const AggView *d_views, const AggTask *d_tasks, int ntasks, int K,
                      uint8_t *base, int *d_counter, int persistent_blocks, hipStream_t st,
-                     int chains_per_block = 16, int prefetch = 8, const AggImages *images = nullptr);
+                     int chains_per_block = 16, int prefetch = 8, const AggImages *images = nullptr,
+                     bool packed = false);
 
 }  // namespace sf

@@ -24,6 +24,11 @@ struct CensusArgs {
     float *pack_fl;
 };
 
+// packed = 1 (D = 128 or 256, cost volumes 4-byte aligned): the volume holds
+// 6-bit costs, 0.75 D bytes per pixel, each run of 16 disparities d = 16c ..
+// 16c + 15 as 16 consecutive 6-bit fields (LSB first) in the 12 bytes at byte
+// 12c of its pixel (cost_packed_bytes gives the volume size).  The fused frame
+// and batch paths aggregate from it; the C ABI keeps one byte per cost.
 struct CostArgs {
     const uint64_t *base[STAGE_MAXV];
     const uint64_t *match[STAGE_MAXV];
@@ -31,7 +36,11 @@ struct CostArgs {
     int right[STAGE_MAXV];
     int n, H, W, D;
     int vec;  // store width in bytes (16, 4 or 1), set by launch_cost from D and the pointers' alignment
+    int packed;
 };
+
+inline bool cost_packable(int D) { return D == 128 || D == 256; }
+inline size_t cost_packed_bytes(int H, int W, int D) { return (size_t)H * W * (size_t)(3 * D / 4); }
 
 // WTA over the sum of nslab u8 slabs [nslab][H][W][D] (D a multiple of 8;
 // launch_wta_slabs needs nslab = 8, the diagonal-search launch takes 1..8).

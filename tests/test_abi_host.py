@@ -135,6 +135,13 @@ def test_volume_offset_limit(L):
     expect(L.sf_batch_plan_create(arr, 1, 10, 120, 1, None, 0, 0, ct.byref(plan)), 1, "2^31")
 
 
+def test_tuning_packed_flag_validated(L):
+    """packed must be 0 or 1; a plan refuses anything else before touching a device."""
+    plan = ct.c_void_p()
+    t = _lib.SfAggTuning(16, 8, 0, 0, 2)
+    expect(L.sf_frame_plan_create(64, 64, 128, 10, 120, 1, 0, ct.byref(t), ct.byref(plan)), 1, "packed")
+
+
 def test_frame_autotune_validation(L):
     t = _lib.SfAggTuning()
     ms = ct.c_float()

@@ -36,7 +36,7 @@ def test_traffic_table_from_counter_passes(tmp_path, monkeypatch):
     import bench
 
     cand = bench.tuning_candidates()
-    assert len(cand) == 36 and len(set(cand)) == 36 and cand[0] == (4, 4, 0, 0)
+    assert len(cand) == 72 and len(set(cand)) == 72 and cand[0] == (4, 4, 0, 0, 0)
     agg = "void sf::sgm_tasks_kernel<8, 4, false>(sf::AggView const*)"
     for counter, copy_kib, scale in (("FETCH_SIZE", 524288.0, 1.0), ("WRITE_SIZE", 1048576.0, 2.0)):
         rows = [("__amd_rocclr_copyBuffer", copy_kib)] * 3 + [("__amd_rocclr_copyBuffer", 10.0)]
@@ -60,11 +60,11 @@ def test_traffic_table_from_counter_passes(tmp_path, monkeypatch):
         # FETCH (i+1) MiB x 2 + WRITE 2 (i+1) MiB x 1 = 4 (i+1) MiB
         assert e["traffic_bytes_per_launch"] == 4 * (i + 1) * (1 << 20)
     monkeypatch.setattr(bench, "TRAFFIC_JSON", out)
-    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 4)) == \
-        rec["by_tuning"]["8,8,1,4"]["traffic_bytes_per_launch"]
-    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 3)) is None
-    assert bench.measured_traffic("sgm_paths", (8, 8, 1, 4)) is None
+    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 4, 1)) == \
+        rec["by_tuning"]["8,8,1,4,1"]["traffic_bytes_per_launch"]
+    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 3, 0)) is None
+    assert bench.measured_traffic("sgm_paths", (8, 8, 1, 4, 0)) is None
     rec["sources_sha256"] = "0" * 64
     with open(out, "w") as f:
         json.dump(rec, f)
-    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 4)) is None
+    assert bench.measured_traffic("sgm_tasks", (8, 8, 1, 4, 1)) is None

@@ -56,13 +56,15 @@ def test_batch_vs_oracle(orc):
         assert_close_rel(host(o["disp"]), d, 1.0)
 
 
-@pytest.mark.parametrize("cpb,pf,order,pers", [(4, 4, 0, 0), (8, 8, 1, 0), (16, 4, 1, 4), (4, 8, 0, 8),
-                                               (16, 8, 0, 2)])
-def test_batch_tunings_and_waves_identical(cpb, pf, order, pers):
-    say("batch tuning", cpb, pf, order, pers)
+@pytest.mark.parametrize("cpb,pf,order,pers,packed", [(4, 4, 0, 0, 0), (8, 8, 1, 0, 1), (16, 4, 1, 4, 0),
+                                                      (4, 8, 0, 8, 1), (16, 8, 0, 2, 1)])
+def test_batch_tunings_and_waves_identical(cpb, pf, order, pers, packed):
+    """Every tuning, 6-bit packed costs included (used by the D = 256 pairs),
+    gives the default plan's maps bit for bit."""
+    say("batch tuning", cpb, pf, order, pers, packed)
     pairs, _ = make_pairs(SIZES)
     ref = [{k: host(v).copy() for k, v in o.items()} for o in batch.Batch(pairs).run()]
-    t = SfAggTuning(cpb, pf, order, pers)
+    t = SfAggTuning(cpb, pf, order, pers, packed)
     b = batch.Batch(pairs, tunings=[t] * 4, mem_budget=8 << 20)  # tiny budget: several waves
     assert b.nwaves > 1
     for rep in range(2):  # twice: a persistent launch leaves its task counter at zero
@@ -76,7 +78,7 @@ def test_batch_tunings_and_waves_identical(cpb, pf, order, pers):
                 assert np.array_equal(host(o[k]), r[k]), (rep, k)
 
 
-@pytest.mark.parametrize("tuning", [None, (8, 8, 0, 4)])
+@pytest.mark.parametrize("tuning", [None, (8, 8, 0, 4, 1)])
 def test_graph_replays_match_eager(tuning):
     """Replays of the captured batch equal the eager run, also with a persistent
     aggregation, whose task counter is reset by the launch itself (the graph
@@ -123,11 +125,10 @@ def test_autotune_returns_valid_choice(tmp_path):
     say("autotune")
     t, ms = batch.autotune(96, 320, 32, cache=str(tmp_path / "at.json"))
     assert t.chains_per_block in (4, 8, 16) and t.prefetch in (4, 8)
-    assert t.order in (0, 1) and 0 <= t.persistent_per_cu <= 8
+    assert t.order in (0, 1) and 0 <= t.persistent_per_cu <= 8 and t.packed == 0  # D = 32: bytes
     assert ms > 0
     t2, ms2 = batch.autotune(96, 320, 32, cache=str(tmp_path / "at.json"))
-    assert (t2.chains_per_block, t2.prefetch, t2.order, t2.persistent_per_cu) == \
-        (t.chains_per_block, t.prefetch, t.order, t.persistent_per_cu)
+    assert batch.tuning_dict(t2) == batch.tuning_dict(t)
 
 
 def test_frame_autotune_returns_valid_choice(tmp_path):
@@ -135,14 +136,13 @@ def test_frame_autotune_returns_valid_choice(tmp_path):
     from paper_1801_04720_amd.pipeline import FusedFrame
 
     say("frame autotune")
-    H, W, D = 48, 160, 32
+    H, W, D = 48, 160, 128
     t, ms = batch.frame_autotune(H, W, D, cache=str(tmp_path / "ft.json"))
     assert t.chains_per_block in (4, 8, 16) and t.prefetch in (4, 8)
-    assert t.order in (0, 1) and t.persistent_per_cu in (0, 4, 8)
+    assert t.order in (0, 1) and t.persistent_per_cu in (0, 4, 8) and t.packed in (0, 1)
     assert ms > 0
     t2, _ = batch.frame_autotune(H, W, D, cache=str(tmp_path / "ft.json"))
-    assert (t2.chains_per_block, t2.prefetch, t2.order, t2.persistent_per_cu) == \
-        (t.chains_per_block, t.prefetch, t.order, t.persistent_per_cu)
+    assert batch.tuning_dict(t2) == batch.tuning_dict(t)
     fr = synth.frame_planar(synth.rng_for(8, 31), H, W, D, 10.0)
     args = [dev(a) for a in (fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right, fr.flow)]
     a = FusedFrame(H, W, D, device=DEV).run(*args)

@@ -47,7 +47,8 @@ def check_frame(got, ref):
 
 
 @pytest.mark.parametrize("H,W,D,persistent", [(48, 160, 32, False), (61, 203, 64, True),
-                                              (40, 97, 96, False), (33, 300, 256, True)])
+                                              (40, 97, 96, False), (29, 211, 128, False),
+                                              (33, 300, 256, True)])
 def test_fused_frame_small(orc, H, W, D, persistent):
     say("fused frame", H, W, D, persistent)
     fr = synth.frame_planar(synth.rng_for(8, D), H, W, D, 20.0)
@@ -140,14 +141,15 @@ def test_fused_frame_repeatable():
             assert np.array_equal(got[k], ref[k], equal_nan=True), (rep, k)
 
 
-def test_learned_frame_equals_stagewise(orc):
+@pytest.mark.parametrize("D", [64, 128])
+def test_learned_frame_equals_stagewise(orc, D):
     """Learned frame == its stages called one by one through the C ABI (each stage is
     pinned against the oracle in its own tests); the plain left maps agree with the
     oracle's WTA, and the learned masks never keep a pixel with x - d* < 0."""
     from paper_1801_04720_amd import api, lrnet
 
-    say("learned frame vs stage-by-stage")
-    H, W, D = 64, 200, 64
+    say("learned frame vs stage-by-stage, D =", D)
+    H, W = 64, 200
     fr = synth.frame_planar(synth.rng_for(8, 11), H, W, D, 25.0)
     prm = dev(lrnet.init_params(5))
     args = [dev(fr.t0.left), dev(fr.t0.right), dev(fr.t1.left), dev(fr.t1.right), dev(fr.flow)]
