@@ -37,14 +37,15 @@ ProfScope::ProfScope(const char *name, hipStream_t st) : st_(st), idx_(-1)
     if (!g_prof_only.empty() && g_prof_only != name) return;
     ProfRec r{name, g_prof_pool[g_prof_next], g_prof_pool[g_prof_next + 1]};
     g_prof_next += 2;
-    hipEventRecord(r.start, st);
+    if (hipEventRecord(r.start, st) != hipSuccess) return;  // the timer is optional: this launch goes untimed
     idx_ = (int)g_prof_recs.size();
     g_prof_recs.push_back(r);
 }
 
 ProfScope::~ProfScope()
 {
-    if (idx_ >= 0) hipEventRecord(g_prof_recs[idx_].stop, st_);
+    // A failed stop record shows up as an error of sf_prof_query for this launch.
+    if (idx_ >= 0) (void)hipEventRecord(g_prof_recs[idx_].stop, st_);
 }
 
 }  // namespace sf
@@ -55,7 +56,7 @@ extern "C" int sf_prof_enable(int max_launches)
     clear_error();
     SF_REQUIRE(max_launches > 0 && max_launches <= (1 << 20), SF_EINVAL,
                "sf_prof_enable: max_launches out of range");
-    for (hipEvent_t e : g_prof_pool) hipEventDestroy(e);
+    for (hipEvent_t e : g_prof_pool) (void)hipEventDestroy(e);
     g_prof_pool.assign((size_t)2 * max_launches, nullptr);
     for (auto &e : g_prof_pool)
         // Timing-only events: no system-scope fence when one is recorded between

@@ -361,8 +361,8 @@ extern "C" int sf_batch_capture(sf_plan plan, void *workspace, size_t ws_bytes, 
     SF_REQUIRE(ws_bytes >= p->ws_bytes, SF_ENOMEM, "sf_batch_capture: workspace too small");
     SF_REQUIRE(stream, SF_EINVAL, "sf_batch_capture: capture needs a non-default stream");
     BatchData &B = *p->batch;
-    if (B.exec) { hipGraphExecDestroy(B.exec); B.exec = nullptr; }
-    if (B.graph) { hipGraphDestroy(B.graph); B.graph = nullptr; }
+    if (B.exec) { (void)hipGraphExecDestroy(B.exec); B.exec = nullptr; }
+    if (B.graph) { (void)hipGraphDestroy(B.graph); B.graph = nullptr; }
     hipStream_t st = as_stream(stream);
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(SF_EHIP, "sf_batch_capture: hipStreamBeginCapture failed");
@@ -370,12 +370,12 @@ extern "C" int sf_batch_capture(sf_plan plan, void *workspace, size_t ws_bytes, 
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess || !g) return fail(SF_EHIP, "sf_batch_capture: hipStreamEndCapture failed");
     if (hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(SF_EHIP, "sf_batch_capture: hipGraphInstantiate failed");
     }
     B.graph = g;
@@ -399,8 +399,8 @@ namespace sf {
 void destroy_batch(BatchData *b)
 {
     if (!b) return;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     delete b;
 }
 }  // namespace sf
@@ -425,9 +425,12 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
     for (int v = 0; v < nviews; ++v)
         hipLaunchKernelGGL(fill_random_cost_kernel, dim3(4096), dim3(256), 0, st, ws + v * vbytes, ncell,
                            1234u + v);
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(ws);
+        return fail(SF_EHIP, "sf_agg_autotune: hipEventCreate");
+    }
     const int ncu = cu_count();
     float best_t = 1e30f;
     int rc = SF_OK;
@@ -450,9 +453,16 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
             uint8_t *tab = nullptr;
             const size_t bv = al256(views.size() * sizeof(AggView)), bt = al256(tasks.size() * sizeof(AggTask));
             if (hipMalloc(&tab, bv + bt + 256) != hipSuccess) { rc = fail(SF_EHIP, "sf_agg_autotune: hipMalloc"); break; }
-            hipMemcpy(tab, views.data(), views.size() * sizeof(AggView), hipMemcpyHostToDevice);
-            hipMemcpy(tab + bv, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice);
-            hipMemset(tab + bv + bt, 0, sizeof(int));  // the persistent counter starts at 0
+            // The tables and the persistent counter (which starts at 0) must be in
+            // place before any launch reads them.
+            if (hipMemcpy(tab, views.data(), views.size() * sizeof(AggView), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(tab + bv, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                hipMemset(tab + bv + bt, 0, sizeof(int)) != hipSuccess) {
+                rc = fail(SF_EHIP, "sf_agg_autotune: task table upload");
+                (void)hipFree(tab);
+                break;
+            }
             for (int pf : prefs)
                 for (int pp : pers)
                     for (int pk = 0; pk <= (cost_packable(D) ? 1 : 0) && rc == SF_OK; ++pk) {
@@ -470,11 +480,11 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
                         for (int v = 0; v < nviews; ++v)
                             hipLaunchKernelGGL(fill_random_cost_kernel, dim3(4096), dim3(256), 0, st,
                                                ws + v * vbytes, ncell, 1234u + v);
-                        hipEventRecord(e0, st);
-                        rc = go();
-                        hipEventRecord(e1, st);
-                        hipEventSynchronize(e1);
-                        hipEventElapsedTime(&tms[rep], e0, e1);
+                        if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SF_EHIP, "sf_agg_autotune: event"); break; }
+                        if ((rc = go())) break;
+                        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&tms[rep], e0, e1) != hipSuccess)
+                            rc = fail(SF_EHIP, "sf_agg_autotune: event timing");
                     }
                     if (rc) break;
                     std::sort(tms, tms + 5);
@@ -483,11 +493,11 @@ extern "C" int sf_agg_autotune(int H, int W, int D, int P1, int P2, int nviews, 
                         *best = sf_agg_tuning{cpb, pf, order, pp, pk};
                     }
                 }
-            hipFree(tab);
+            (void)hipFree(tab);
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(ws);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(ws);
     if (rc) return rc;
     if (best_ms) *best_ms = best_t;
     return SF_OK;

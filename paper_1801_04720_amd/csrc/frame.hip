@@ -164,7 +164,7 @@ extern "C" int sf_plan_destroy(sf_plan plan)
 {
     if (!plan) return SF_OK;
     Plan *p = reinterpret_cast<Plan *>(plan);
-    if (p->d_tables) hipFree(p->d_tables);
+    if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->batch) destroy_batch(p->batch);
     delete p;
     return SF_OK;
@@ -468,9 +468,12 @@ extern "C" int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol
         return sf_frame_run(pl, img[0], img[1], img[2], img[3], W, flow, &cam, d0, buf + o_v0, d1,
                             buf + o_v1, sf, buf + o_v, xyz, mot, buf + o_ws, ws_bytes, stream);
     };
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        (void)hipFree(buf);
+        return fail(SF_EHIP, "sf_frame_autotune: hipEventCreate");
+    }
     float best_t = 1e30f;
     // Candidates: packed costs (where D allows) x chains per block x order x prefetch x
     // persistent blocks per CU.
@@ -487,11 +490,12 @@ extern "C" int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol
         for (int w = 0; w < 2 && rc == SF_OK; ++w) rc = run(pl);
         float tms[REPS];
         for (int r = 0; r < REPS && rc == SF_OK; ++r) {
-            hipEventRecord(e0, st);
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SF_EHIP, "sf_frame_autotune: event"); break; }
             for (int f = 0; f < FRAMES && rc == SF_OK; ++f) rc = run(pl);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
-            hipEventElapsedTime(&tms[r], e0, e1);
+            if (rc) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&tms[r], e0, e1) != hipSuccess)
+                rc = fail(SF_EHIP, "sf_frame_autotune: event timing");
             tms[r] /= FRAMES;
         }
         sf_plan_destroy(pl);
@@ -502,9 +506,9 @@ extern "C" int sf_frame_autotune(int H, int W, int D, int P1, int P2, int lr_tol
             *best = cand[c];
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(buf);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
     if (rc) return rc;
     if (best_ms) *best_ms = best_t;
     return SF_OK;
