@@ -42,6 +42,9 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "sgm_tasks_frame_1242x375_traffic.
 TRAFFIC_SOURCES = ["paper_1801_04720_amd/csrc/sgm.hip", "paper_1801_04720_amd/csrc/sgm_tasks.hpp",
                    "paper_1801_04720_amd/csrc/sf_internal.hpp", "paper_1801_04720_amd/csrc/frame.hip"]
 SWEEP_FRAMES = 2   # frames per tuning in --tuning-sweep; the counters of the last one are kept
+# Where the bench legs cache the autotuners' choices (machine-specific, not part of the
+# repository); later runs on the same machine reuse them.
+TUNE_CACHE = os.environ.get("SF_TUNE_CACHE", os.path.join(ROOT, ".tune_cache", "autotune_cache.json"))
 
 
 def tuning_candidates():
@@ -127,10 +130,9 @@ def write_traffic_table(fetch_db, write_db, out=TRAFFIC_JSON):
            "copy_calibration": {"bytes": 1 << 30, "fetch_size_kib": cf, "write_size_kib": cw,
                                 "fetch_factor": ff, "write_factor": fw},
            "by_tuning": table,
-           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmt -o fetch -- {sweep}",
-                        f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmt -o write -- {sweep}",
-                        "python3 bench.py --traffic-from gpurun_out/pmt/fetch_results.db "
-                        "gpurun_out/pmt/write_results.db"]}
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {os.path.dirname(fetch_db) or '.'} -o fetch -- {sweep}",
+                        f"rocprofv3 --pmc WRITE_SIZE -d {os.path.dirname(write_db) or '.'} -o write -- {sweep}",
+                        f"python3 bench.py --traffic-from {fetch_db} {write_db}"]}
     with open(out, "w") as fo:
         json.dump(rec, fo, indent=1)
     tb = [e["traffic_bytes_per_launch"] / 1e9 for e in table.values()]
@@ -234,7 +236,7 @@ def bench_batch(args, dev):
     tunings, tune_info = {}, {}
     for (H, W, D) in classes:
         t, ms = batch.autotune(H, W, D, nviews=2,
-                               cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+                               cache=TUNE_CACHE)
         tunings[(H, W, D)] = t
         tune_info[f"{W}x{H}xD{D}"] = dict(batch.tuning_dict(t), aggregation_ms_per_pair=ms)
     budget = int(args.mem_budget_gb * (1 << 30))
@@ -347,7 +349,7 @@ def bench_stream(args, dev):
     frames = [tuple(a.to(dev) for a in f) for f in host]
     with np.load(args.lrnet, allow_pickle=False) as z:
         prm = torch.from_numpy(z["params"].astype(np.float32)).to(dev)
-    cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+    cache = TUNE_CACHE
     t2, _ = batch.frame_autotune(H, W, D, flags=api.FRAME_LEARNED, cache=cache)
     t4, _ = batch.frame_autotune(H, W, D, cache=cache)
     learned = FusedFrame(H, W, D, learned_params=prm, tuning=t2, device=dev)
@@ -505,7 +507,7 @@ def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
         from paper_1801_04720_amd import batch
 
         tuning, _ = batch.frame_autotune(H, W, D, flags=api.FRAME_LEARNED,
-                                         cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+                                         cache=TUNE_CACHE)
     lp = FusedFrame(H, W, D, learned_params=prm_t, tuning=tuning, device=dev)
     for _ in range(args.warmup):
         lp.run(*inputs)
@@ -546,7 +548,7 @@ def variants_leg(args, plain_pipe, inputs, fr, H, W, D, ms_plain, dev):
     if tuned:
         from paper_1801_04720_amd import batch
 
-        cache = os.path.join(ROOT, "gpurun_out", "autotune_cache.json")
+        cache = TUNE_CACHE
     gt = torch.from_numpy(fr.t0.gt_disp).to(dev)
     plain = plain_pipe.run(*inputs)
     plain = {k: plain[k].clone() for k in ("valid0", "valid1", "disp0", "sf4", "valid")}
@@ -827,7 +829,7 @@ def main():
         from paper_1801_04720_amd import batch
 
         tuning, t_ms = batch.frame_autotune(H, W, D,
-                                            cache=os.path.join(ROOT, "gpurun_out", "autotune_cache.json"))
+                                            cache=TUNE_CACHE)
         tuning_info = dict(batch.tuning_dict(tuning), tuner_ms=t_ms)
     if args.pipeline == "stages":
         pipe = PlainFrame(H, W, D, device=dev)
