@@ -176,10 +176,14 @@ def test_learned_frame_equals_stagewise(orc, D):
     assert not (got["valid0"].astype(bool) & ((xs - w0) < 0)).any()
 
 
+@pytest.mark.parametrize("D", [32, 128])
 @pytest.mark.parametrize("H,W", [(1, 1), (1, 50), (50, 1), (7, 9)])
-def test_fused_frame_degenerate_shapes(orc, H, W):
-    say("fused frame degenerate", H, W)
-    D = 32
+def test_fused_frame_degenerate_shapes(orc, H, W, D):
+    """Frames smaller than one tile; at D = 128 with packed costs and a persistent
+    launch, whose task count is then below the block count it asks for."""
+    from paper_1801_04720_amd._lib import SfAggTuning
+
+    say("fused frame degenerate", H, W, D)
     rng = np.random.default_rng(H * 100 + W)
     imgs = [rng.integers(0, 256, (H, W)).astype(np.uint8) for _ in range(4)]
     flow = rng.normal(0, 2, (H, W, 2)).astype(np.float32)
@@ -191,10 +195,12 @@ def test_fused_frame_degenerate_shapes(orc, H, W):
     fr.t0, fr.t1 = F(), F()
     fr.t0.left, fr.t0.right, fr.t1.left, fr.t1.right = imgs
     fr.flow = flow
-    ff = FusedFrame(H, W, D, device=DEV)
-    got = ff.run(dev(imgs[0]), dev(imgs[1]), dev(imgs[2]), dev(imgs[3]), dev(flow))
-    torch.cuda.synchronize()
-    check_frame(got, oracle_frame(orc, fr, D, ff.cam))
+    tuning = SfAggTuning(16, 8, 0, 4, 1) if D == 128 else None
+    ff = FusedFrame(H, W, D, tuning=tuning, device=DEV)
+    for _ in range(2):  # twice: the persistent counter must be back at zero
+        got = ff.run(dev(imgs[0]), dev(imgs[1]), dev(imgs[2]), dev(imgs[3]), dev(flow))
+        torch.cuda.synchronize()
+        check_frame(got, oracle_frame(orc, fr, D, ff.cam))
 
 
 def test_fused_frame_max_size_vs_stagewise():
