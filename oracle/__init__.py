@@ -68,6 +68,9 @@ def _declare(L):
     L.oracle_splitmix64.argtypes = [ct.c_uint64, ct.c_uint64]
     L.oracle_splitmix64.restype = ct.c_uint64
     L.oracle_pyr_down.argtypes = [P, I, I, P]
+    L.oracle_pm_offset.argtypes = [ct.c_uint64, I, I, I, I, I, I, P, P]
+    L.oracle_pm_pixel.argtypes = [P, P, I, I, I, I, I, ct.c_uint64, P, I, I, P, P, P, I]
+    L.oracle_pm_pixel.restype = I
     L.oracle_flow_cost.argtypes = [P, P, I, I, I, I, I, I]
     L.oracle_pm_flow.argtypes = [P, P, I, I, I, I, I, I, ct.c_uint64, P]
     L.oracle_fb_check.argtypes = [P, P, I, I, I, P]
@@ -282,6 +285,28 @@ def pyr_down(img):
     out = np.zeros(((H + 1) // 2, (W + 1) // 2), np.uint8)
     lib().oracle_pyr_down(_p(a), H, W, _p(out))
     return out
+
+
+def pm_offset(seed, level, it, k, x, y, r):
+    """Random-search offset (u, v) of candidate k with radius r at pixel (x, y)."""
+    ou, ov = ct.c_int(0), ct.c_int(0)
+    lib().oracle_pm_offset(seed, level, it, k, x, y, r, ct.byref(ou), ct.byref(ov))
+    return ou.value, ov.value
+
+
+def pm_pixel(c0, c1, level, it, Rl, seed, fin, x, y, max_trace=64):
+    """One pixel of one search iteration: the winner (u, v) and the evaluated
+    candidates as rows (u, v, cost), in evaluation order."""
+    a = np.ascontiguousarray(c0, np.uint64)
+    b = np.ascontiguousarray(c1, np.uint64)
+    f = np.ascontiguousarray(fin, np.int16)
+    H, W = a.shape
+    tr = np.zeros((max_trace, 3), np.int32)
+    bu, bv = ct.c_int(0), ct.c_int(0)
+    n = lib().oracle_pm_pixel(_p(a), _p(b), H, W, level, it, Rl, seed, _p(f), x, y, ct.byref(bu),
+                              ct.byref(bv), _p(tr), max_trace)
+    assert n <= max_trace
+    return (bu.value, bv.value), tr[:n]
 
 
 def flow_cost(c0, c1, x, y, fu, fv):

@@ -33,7 +33,13 @@
  *     c = (((level * 64 + iter) * 64 + k) * 65536 + y/8) * 65536 + x/8, so
  *     the pixels of one 8x8 tile share the offset (each still searches around
  *     its own best flow); the offset is ((h & 0xFFFF) mod (2r+1)) - r
- *     horizontally and (((h >> 16) & 0xFFFF) mod (2r+1)) - r vertically;
+ *     horizontally and (((h >> 16) & 0xFFFF) mod (2r+1)) - r vertically.
+ *     Sec. 3.2 names random search but not its distribution: this definition
+ *     gives every pixel a candidate spread over the (2r+1)^2 box around its
+ *     own best flow (up to the 16-bit modulo bias), and draws one displacement
+ *     per tile, so that neighbouring pixels try the same relative move of
+ *     their own matches.  Per-pixel draws would be an equally valid choice;
+ *     this one is fixed here and the kernels follow it;
  *   - consistency: forward flow F at x is kept iff the backward flow B (the
  *     same method from the second image to the first, with seed
  *     seed ^ 0x5bd1e995) at x' = x + F(x)
@@ -97,48 +103,86 @@ int oracle_flow_cost(const uint64_t *c0, const uint64_t *c1, int H, int W, int x
     return s;
 }
 
+/* Random-search offset of candidate k (radius r) at pixel (x, y) of the given
+ * level and iteration: the counter packs (level, iteration, k, tile row, tile
+ * column) with the 8x8 tile of the pixel; the low 16 bits of the generator's
+ * output give the horizontal offset, the next 16 bits the vertical one. */
+void oracle_pm_offset(uint64_t seed, int level, int iter, int k, int x, int y, int r, int *ou, int *ov)
+{
+    const uint64_t ctr =
+        ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)(y / 8)) * 65536 +
+        (uint64_t)(x / 8);
+    const uint64_t h = oracle_splitmix64(seed, ctr);
+    *ou = (int)((h & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;
+    *ov = (int)(((h >> 16) & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;
+}
+
+/* One pixel of one iteration: evaluates the candidates in their order and
+ * returns how many it evaluated; *bu, *bv receive the winner.  When trace is
+ * not NULL, candidate n is recorded as trace[3n .. 3n+2] = (u, v, cost) for
+ * the first max_trace candidates (cost -1: target outside the image). */
+int oracle_pm_pixel(const uint64_t *c0, const uint64_t *c1, int H, int W, int level, int iter, int Rl,
+                    uint64_t seed, const int16_t *fin, int x, int y, int *bu_out, int *bv_out, int *trace,
+                    int max_trace)
+{
+    const int du[4] = {-1, +1, 0, 0}, dv[4] = {0, 0, -1, +1};
+    const int dist[2] = {1, 4};
+    int n = 0;
+#define PM_RECORD(U, V, C)                  \
+    do {                                    \
+        if (trace && n < max_trace) {       \
+            trace[3 * n] = (U);             \
+            trace[3 * n + 1] = (V);         \
+            trace[3 * n + 2] = (C);         \
+        }                                   \
+        ++n;                                \
+    } while (0)
+    const size_t i = (size_t)y * W + x;
+    int bu = fin[2 * i], bv = fin[2 * i + 1];
+    int best = oracle_flow_cost(c0, c1, H, W, x, y, bu, bv);
+    PM_RECORD(bu, bv, best);
+    if (best < 0) best = 1 << 30; /* cannot happen: fields keep targets inside */
+    for (int s = 0; s < 2; ++s)
+        for (int m = 0; m < 4; ++m) {
+            const int nx = x + dist[s] * du[m], ny = y + dist[s] * dv[m];
+            if (nx < 0 || nx > W - 1 || ny < 0 || ny > H - 1) continue;
+            const size_t k = (size_t)ny * W + nx;
+            const int cu = fin[2 * k], cv = fin[2 * k + 1];
+            const int c = oracle_flow_cost(c0, c1, H, W, x, y, cu, cv);
+            PM_RECORD(cu, cv, c);
+            if (c >= 0 && c < best) {
+                best = c;
+                bu = cu;
+                bv = cv;
+            }
+        }
+    for (int k = 0; (Rl >> k) >= 1; ++k) {
+        int ou, ov;
+        oracle_pm_offset(seed, level, iter, k, x, y, Rl >> k, &ou, &ov);
+        const int cu = bu + ou, cv = bv + ov;
+        const int c = oracle_flow_cost(c0, c1, H, W, x, y, cu, cv);
+        PM_RECORD(cu, cv, c);
+        if (c >= 0 && c < best) {
+            best = c;
+            bu = cu;
+            bv = cv;
+        }
+    }
+#undef PM_RECORD
+    *bu_out = bu;
+    *bv_out = bv;
+    return n;
+}
+
 /* One iteration on one level: flow_in / flow_out [H][W][2] int16. */
 static void pm_iteration(const uint64_t *c0, const uint64_t *c1, int H, int W, int level, int iter,
                          int Rl, uint64_t seed, const int16_t *fin, int16_t *fout)
 {
-    const int du[4] = {-1, +1, 0, 0}, dv[4] = {0, 0, -1, +1};
-    const int dist[2] = {1, 4};
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
             const size_t i = (size_t)y * W + x;
-            int bu = fin[2 * i], bv = fin[2 * i + 1];
-            int best = oracle_flow_cost(c0, c1, H, W, x, y, bu, bv);
-            if (best < 0) best = 1 << 30; /* cannot happen: fields keep targets inside */
-            for (int s = 0; s < 2; ++s)
-                for (int n = 0; n < 4; ++n) {
-                    const int nx = x + dist[s] * du[n], ny = y + dist[s] * dv[n];
-                    if (nx < 0 || nx > W - 1 || ny < 0 || ny > H - 1) continue;
-                    const size_t k = (size_t)ny * W + nx;
-                    const int cu = fin[2 * k], cv = fin[2 * k + 1];
-                    const int c = oracle_flow_cost(c0, c1, H, W, x, y, cu, cv);
-                    if (c >= 0 && c < best) {
-                        best = c;
-                        bu = cu;
-                        bv = cv;
-                    }
-                }
-            for (int k = 0; (Rl >> k) >= 1; ++k) {
-                const int r = Rl >> k;
-                const uint64_t ctr =
-                    ((((uint64_t)level * 64 + (uint64_t)iter) * 64 + (uint64_t)k) * 65536 + (uint64_t)(y / 8)) *
-                        65536 +
-                    (uint64_t)(x / 8);
-                const uint64_t h = oracle_splitmix64(seed, ctr);
-                const int ou = (int)((h & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;
-                const int ov = (int)(((h >> 16) & 0xFFFFu) % (uint64_t)(2 * r + 1)) - r;
-                const int cu = bu + ou, cv = bv + ov;
-                const int c = oracle_flow_cost(c0, c1, H, W, x, y, cu, cv);
-                if (c >= 0 && c < best) {
-                    best = c;
-                    bu = cu;
-                    bv = cv;
-                }
-            }
+            int bu, bv;
+            oracle_pm_pixel(c0, c1, H, W, level, iter, Rl, seed, fin, x, y, &bu, &bv, NULL, 0);
             fout[2 * i] = (int16_t)bu;
             fout[2 * i + 1] = (int16_t)bv;
         }
