@@ -277,6 +277,13 @@ int sf_frame_run_learned(sf_plan plan, const uint8_t *L0, const uint8_t *R0, con
                          uint8_t *valid1, float *sf4, uint8_t *valid, float *xyz0, float *motion,
                          void *workspace, size_t ws_bytes, void *stream);
 
+/* Judge of the learned stand-in against the left-right check it imitates
+ * (Sec. 3.1): *count (device u32, output) = the number of i < n where a[i] and
+ * b[i] (device uint8 masks, any alignment) are both zero or both nonzero.
+ * One small launch on `stream`; the count is deterministic and needs no
+ * clearing.  SF_EINVAL on a NULL pointer or n <= 0. */
+int sf_mask_agreement(const uint8_t *a, const uint8_t *b, int n, uint32_t *count, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Batched plain SGM: many stereo pairs of uneven size and disparity range, each
  * processed exactly as a plain pair (census, both cost volumes, 8-path
@@ -348,6 +355,13 @@ int sf_lrnet_mask(const float *logits, const int16_t *wta, const float *dsub, in
  * (bit-reproducible run to run). */
 int sf_lrnet_grad(const float *params, const float *feat, const uint8_t *label, int B, int H, int W,
                   float *grad, float *loss, void *workspace, size_t ws_bytes, void *stream);
+/* The same backward from a given dL/dz4 [B][H][W] FP32 (device, caller-owned)
+ * instead of the loss: the forward recomputes the activations, then the four
+ * layers' gradients follow exactly as in sf_lrnet_grad.  grad [5377] FP32
+ * (output).  Workspace: sf_lrnet_workspace_bytes(B, H, W, 1).  SF_EINVAL on a
+ * NULL pointer or a bad size, SF_ENOMEM on a short workspace. */
+int sf_lrnet_backward(const float *params, const float *feat, const float *dz4, int B, int H, int W,
+                      float *grad, void *workspace, size_t ws_bytes, void *stream);
 /* Adam in FP32, in place, in this order: m = b1 m + (1-b1) g; v = b2 v + (1-b2) g g;
  * w -= (lr m/(1-b1t)) / (sqrt(v/(1-b2t)) + eps); b1t, b2t = b1, b2 to the step count. */
 int sf_lrnet_adam(float *params, float *m, float *v, const float *grad, int n, float lr, float b1,

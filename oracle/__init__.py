@@ -79,6 +79,7 @@ def _declare(L):
     L.oracle_lrnet.argtypes = [P, P, I, I, I, P, I, P, P]
     L.oracle_lrnet.restype = ct.c_double
     L.oracle_lrnet_nparams.restype = I
+    L.oracle_lrnet_backward.argtypes = [P, P, I, I, I, P, I, P]
     L.oracle_bf16.argtypes = [F]
     L.oracle_bf16.restype = F
     L.oracle_adam.argtypes = [P, P, P, P, I, F, F, F, F, F, F]
@@ -399,6 +400,19 @@ def lrnet(feat, params, label=None, round_bf16=True, want_grad=False):
                               int(round_bf16), _p(grad) if grad is not None else None,
                               _p(logits))
     return loss, logits, grad
+
+
+def lrnet_backward(feat, dz4, params, round_bf16=True):
+    """Parameter gradient [5377] of the network for a given dL/dz4 [B][H][W]."""
+    f = np.ascontiguousarray(feat, np.float32)
+    if f.ndim == 3:
+        f = f[None]
+    B, H, W, _ = f.shape
+    g = np.ascontiguousarray(dz4, np.float32).reshape(B, H, W)
+    prm = np.ascontiguousarray(params, np.float32)
+    grad = np.zeros(NPARAM, np.float32)
+    lib().oracle_lrnet_backward(_p(f), _p(g), B, H, W, _p(prm), int(round_bf16), _p(grad))
+    return grad
 
 
 def bf16(x: np.ndarray) -> np.ndarray:

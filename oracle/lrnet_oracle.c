@@ -173,8 +173,25 @@ static void conv_bwd_weight(const float *gz, int Cout, int H, int W, const float
  * NULL), params [5377] FP32 master weights.  logits [B][H][W] (optional).
  * Returns the mean loss (or 0 when label is NULL).  grad [5377] FP32.
  */
+static double lrnet_run(const float *feat, const uint8_t *label, const float *dz4, int B, int H,
+                        int W, const float *params, int round_bf16, float *grad, float *logits);
+
 double oracle_lrnet(const float *feat, const uint8_t *label, int B, int H, int W,
                     const float *params, int round_bf16, float *grad, float *logits)
+{
+    return lrnet_run(feat, label, NULL, B, H, W, params, round_bf16, grad, logits);
+}
+
+/* Backward from a given dL/dz4 [B][H][W] (FP32) instead of the loss: the same
+ * forward, then the same backward steps as oracle_lrnet with g4 := dz4. */
+void oracle_lrnet_backward(const float *feat, const float *dz4, int B, int H, int W,
+                           const float *params, int round_bf16, float *grad)
+{
+    lrnet_run(feat, NULL, dz4, B, H, W, params, round_bf16, grad, NULL);
+}
+
+static double lrnet_run(const float *feat, const uint8_t *label, const float *dz4, int B, int H,
+                        int W, const float *params, int round_bf16, float *grad, float *logits)
 {
     size_t hw = (size_t)H * W;
     float wq[NPARAM];
@@ -207,15 +224,19 @@ double oracle_lrnet(const float *feat, const uint8_t *label, int B, int H, int W
         for (size_t i = 0; i < 16 * hw; ++i) a3[i] = maybe_bf16(z3[i] > 0.0f ? z3[i] : 0.0f, round_bf16);
         conv_fwd(a3, 16, H, W, wq + OFF_W4, wq + OFF_B4, 1, z4);
         if (logits) memcpy(logits + (size_t)bi * hw, z4, hw * 4);
-        if (!label) continue;
-        const uint8_t *lb = label + (size_t)bi * hw;
-        for (size_t p = 0; p < hw; ++p) {
-            double z = z4[p], y = lb[p] ? 1.0 : 0.0;
-            /* softplus(z) - y z, evaluated without overflow */
-            double sp = z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));
-            loss += sp - y * z;
-            double s = 1.0 / (1.0 + exp(-z));
-            g4[p] = (float)((s - y) / ntot);
+        if (dz4) {
+            memcpy(g4, dz4 + (size_t)bi * hw, hw * 4);
+        } else {
+            if (!label) continue;
+            const uint8_t *lb = label + (size_t)bi * hw;
+            for (size_t p = 0; p < hw; ++p) {
+                double z = z4[p], y = lb[p] ? 1.0 : 0.0;
+                /* softplus(z) - y z, evaluated without overflow */
+                double sp = z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));
+                loss += sp - y * z;
+                double s = 1.0 / (1.0 + exp(-z));
+                g4[p] = (float)((s - y) / ntot);
+            }
         }
         if (!grad) continue;
         /* layer 4 */

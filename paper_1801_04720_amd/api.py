@@ -259,6 +259,15 @@ def flow(L0, L1, levels: int = 5, iters: int = 6, R: int = 128, seed: int = 1801
     return {"flow": fl, "F": F, "B": B, "workspace": ws}
 
 
+def mask_agreement(a, b, out=None, stream=None):
+    """Device u32 count of the pixels where masks a and b agree (sf_mask_agreement)."""
+    if out is None:
+        out = torch.empty(1, dtype=torch.int32, device=a.device)
+    assert a.numel() == b.numel()
+    check(lib().sf_mask_agreement(_ptr(a), _ptr(b), a.numel(), _ptr(out), _stream(stream)))
+    return out
+
+
 FRAME_PERSISTENT, FRAME_LEARNED, FRAME_DIAG, FRAME_MEDIAN, FRAME_ADAPTIVE_P2 = 1, 2, 4, 8, 16
 
 

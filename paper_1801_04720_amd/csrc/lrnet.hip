@@ -804,6 +804,9 @@ extern "C" int sf_lrnet_mask(const float *logits, const int16_t *wta, const floa
     return launch_lr_mask(logits, wta, dsub, H, W, valid, disp, as_stream(stream));
 }
 
+static int lr_backward(const float *params, const float *feat, const float *g4, int B, int H, int W,
+                       uint8_t *ws, const LrLayout &L, float *grad, hipStream_t st);
+
 extern "C" int sf_lrnet_grad(const float *params, const float *feat, const uint8_t *label, int B,
                              int H, int W, float *grad, float *loss, void *workspace,
                              size_t ws_bytes, void *stream)
@@ -820,6 +823,36 @@ extern "C" int sf_lrnet_grad(const float *params, const float *feat, const uint8
     float *lossp = reinterpret_cast<float *>(ws + L.loss);
     rc = lr_forward(params, feat, B, H, W, ws, L, z, label, g4, lossp, st);
     if (rc) return rc;
+    rc = lr_backward(params, feat, g4, B, H, W, ws, L, grad, st);
+    if (rc) return rc;
+    ProfScope prof("lrnet_loss", st);
+    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, lossp, L.nb4,
+                       1.0f / (float)((double)B * H * W), loss);
+    return launch_status("lrnet loss");
+}
+
+extern "C" int sf_lrnet_backward(const float *params, const float *feat, const float *dz4, int B,
+                                 int H, int W, float *grad, void *workspace, size_t ws_bytes,
+                                 void *stream)
+{
+    clear_error();
+    int rc = lr_check(params, feat, B, H, W, workspace, ws_bytes, true);
+    if (rc) return rc;
+    SF_REQUIRE(dz4 && grad, SF_EINVAL, "sf_lrnet_backward: NULL pointer");
+    hipStream_t st = as_stream(stream);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    const LrLayout L = lr_layout(B, H, W, true);
+    float *z = reinterpret_cast<float *>(ws + L.z);
+    rc = lr_forward(params, feat, B, H, W, ws, L, z, nullptr, nullptr, nullptr, st);
+    if (rc) return rc;
+    return lr_backward(params, feat, dz4, B, H, W, ws, L, grad, st);
+}
+
+// Backward of the four layers from g4 = dL/dz4 [B][H][W], with the forward's
+// BF16 activations a1..a3 in the workspace.
+static int lr_backward(const float *params, const float *feat, const float *g4, int B, int H, int W,
+                       uint8_t *ws, const LrLayout &L, float *grad, hipStream_t st)
+{
     uint16_t *a1 = reinterpret_cast<uint16_t *>(ws + L.a1);
     uint16_t *a2 = reinterpret_cast<uint16_t *>(ws + L.a2);
     uint16_t *a3 = reinterpret_cast<uint16_t *>(ws + L.a3);
@@ -853,8 +886,6 @@ extern "C" int sf_lrnet_grad(const float *params, const float *feat, const uint8
                        reinterpret_cast<const float4 *>(feat), H, W, part);
     hipLaunchKernelGGL(reduce_parts_kernel, dim3(3), dim3(256), 0, st, part, L.nbc, 592, 576,
                        OFF_W1, OFF_B1, grad);
-    hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, lossp, L.nb4,
-                       1.0f / (float)((double)B * H * W), loss);
     return launch_status("lrnet backward");
 }
 

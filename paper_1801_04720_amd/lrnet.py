@@ -1,7 +1,7 @@
 """Binding and training loop of the learned stand-in for the LR check.
 
 Marshalling only: forward, loss/gradient and the Adam step are HIP kernels of
-libsf.so (sf_lrnet_forward / sf_lrnet_grad / sf_lrnet_adam)."""
+libsf.so (sf_lrnet_forward / sf_lrnet_grad / sf_lrnet_backward / sf_lrnet_adam)."""
 from __future__ import annotations
 
 import ctypes as ct
@@ -69,6 +69,19 @@ def grad(params, feat, label, grad_out=None, loss_out=None, workspace=None, stre
     check(lib().sf_lrnet_grad(_ptr(params), _ptr(feat), _ptr(label), B, H, W, _ptr(grad_out),
                               _ptr(loss_out), _ptr(workspace), workspace.numel(), _stream(stream)))
     return grad_out, loss_out
+
+
+def backward(params, feat, dz4, grad_out=None, workspace=None, stream=None):
+    """Parameter gradient for a given dL/dz4 [B][H][W] (sf_lrnet_backward)."""
+    B, H, W, _ = feat.shape
+    dev = feat.device
+    if grad_out is None:
+        grad_out = torch.empty(NPARAM, dtype=torch.float32, device=dev)
+    if workspace is None:
+        workspace = torch.empty(workspace_bytes(B, H, W, True), dtype=torch.uint8, device=dev)
+    check(lib().sf_lrnet_backward(_ptr(params), _ptr(feat), _ptr(dz4), B, H, W, _ptr(grad_out),
+                                  _ptr(workspace), workspace.numel(), _stream(stream)))
+    return grad_out
 
 
 def adam(params, m, v, g, lr, b1, b2, eps, step, stream=None):

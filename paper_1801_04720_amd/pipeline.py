@@ -114,6 +114,53 @@ class FusedFrame:
         return api.frame_run(self.plan, L0, R0, L1, R1, flow, self.cam, self.out, self.ws)
 
 
+class JudgedLearnedStream:
+    """Learned frames with the full left-right check (Sec. 3.1) as judge and as
+    fallback.
+
+    Every `judge_every`-th frame (the first included) runs both the plain frame
+    and the learned frame; the plain result is delivered, and the agreement of
+    the two frames' masks (the lower of the t0 and t1 maps, counted by
+    sf_mask_agreement and read back once per judged frame) sets the mode of
+    the frames up to the next judge: learned frames while it is at least
+    `threshold`, plain frames (the fallback) otherwise.  A fallback frame is
+    the plain frame itself, so its outputs equal the plain frame's bit for bit.
+    `history` holds (frame index, agreement t0, agreement t1, mode chosen)."""
+
+    def __init__(self, H: int, W: int, D: int, params, judge_every: int = 16, threshold: float = 0.99,
+                 tuning_learned=None, tuning_plain=None, device="cuda:0", **kw):
+        if judge_every < 1:
+            raise ValueError("judge_every must be >= 1")
+        self.learned = FusedFrame(H, W, D, learned_params=params, tuning=tuning_learned, device=device, **kw)
+        self.plain = FusedFrame(H, W, D, tuning=tuning_plain, device=device, **kw)
+        self.judge_every, self.threshold = judge_every, float(threshold)
+        self.count = torch.zeros(2, dtype=torch.int32, device=device)
+        self.count_host = torch.zeros(2, dtype=torch.int32).pin_memory()
+        self.npx = H * W
+        self.k = 0
+        self.mode = "learned"
+        self.history = []
+
+    def run(self, L0, R0, L1, R1, flow):
+        judged = self.k % self.judge_every == 0
+        k = self.k
+        self.k += 1
+        if judged:
+            lo = self.learned.run(L0, R0, L1, R1, flow)
+            po = self.plain.run(L0, R0, L1, R1, flow)
+            api.mask_agreement(lo["valid0"], po["valid0"], out=self.count[0:1])
+            api.mask_agreement(lo["valid1"], po["valid1"], out=self.count[1:2])
+            self.count_host.copy_(self.count, non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            a0, a1 = (int(v) / self.npx for v in self.count_host.tolist())
+            self.mode = "learned" if min(a0, a1) >= self.threshold else "plain"
+            self.history.append((k, a0, a1, self.mode))
+            return po
+        if self.mode == "plain":
+            return self.plain.run(L0, R0, L1, R1, flow)
+        return self.learned.run(L0, R0, L1, R1, flow)
+
+
 class SequenceFrames:
     """Scene flow over T time steps of one stereo rig (the paper's future work:
     more than two frame pairs with an intermediate validation): every time

@@ -149,3 +149,11 @@ def test_frame_autotune_validation(L):
     # Invalid plans are refused before any buffer is allocated.
     expect(L.sf_frame_autotune(64, 64, 32, 10, 120, 1, 4 | 2, None, ct.byref(t), ct.byref(ms)), 1, "exclude")
     expect(L.sf_frame_autotune(8192, 1024, 256, 10, 120, 1, 0, None, ct.byref(t), ct.byref(ms)), 1, "2^31")
+
+
+def test_network_and_judge_validation(L):
+    expect(L.sf_lrnet_backward(FAKE, FAKE, None, 1, 4, 4, FAKE, FAKE, 1 << 30, None), 1, "NULL")
+    expect(L.sf_lrnet_backward(FAKE, FAKE, FAKE, 0, 4, 4, FAKE, FAKE, 1 << 30, None), 1, "positive")
+    expect(L.sf_lrnet_backward(FAKE, FAKE, FAKE, 1, 4, 4, FAKE, FAKE, 16, None), 4, "workspace")
+    expect(L.sf_mask_agreement(FAKE, None, 10, FAKE, None), 1, "NULL")
+    expect(L.sf_mask_agreement(FAKE, FAKE, 0, FAKE, None), 1, "positive")

@@ -257,3 +257,27 @@ def test_learned_frame_adaptive_equals_stagewise():
         torch.cuda.synchronize()
         assert np.array_equal(got["valid" + key], host(valid))
         assert np.array_equal(got["disp" + key], host(disp))
+
+
+def steps_image(H, W):
+    """Intensities whose horizontal and vertical steps take every value 1..255."""
+    x = np.arange(W, dtype=np.int64)[None, :]
+    y = np.arange(H, dtype=np.int64)[:, None]
+    return ((x * (x + 1) // 2 + 3 * (y * (y + 1) // 2)) % 256).astype(np.uint8)
+
+
+@pytest.mark.parametrize("D", [32, 64])
+def test_aggregate_adaptive_largest_p2_all_steps(orc, D):
+    """P2 = 8000 (the largest the entry points accept) on an image whose path
+    steps cover g = 1..255: the quotient floor(P2 / g) is exact in every
+    direction (S then needs the packed 16-bit accumulation: 62 + P2 > 255)."""
+    say("aggregate adaptive P2 = 8000, all steps, D =", D)
+    H, W = 270, 300
+    img = steps_image(H, W)
+    gh = set(np.abs(np.diff(img.astype(np.int64), axis=1)).ravel().tolist())
+    gv = set(np.abs(np.diff(img.astype(np.int64), axis=0)).ravel().tolist())
+    assert set(range(1, 256)) <= gh and set(range(1, 256)) <= gv
+    rng = np.random.default_rng(8000 + D)
+    C = rng.integers(0, 63, (H, W, D)).astype(np.uint8)
+    got = host(api.sgm_aggregate_adaptive(dev(C), dev(img), 10, 8000), np.uint16)
+    assert np.array_equal(got, orc.aggregate_adaptive(C, img, 10, 8000))

@@ -3,6 +3,7 @@ gradient's closed form, kernel orientation by a delta input, BF16 rounding
 against the format definition, Adam's first-step closed form, and the feature
 definitions on hand-built cost volumes."""
 import numpy as np
+import pytest
 
 from paper_1801_04720_amd import synth
 
@@ -184,3 +185,29 @@ def test_network_separates_simple_labels(orc):
         orc.adam(prm, m, v, g, 1e-2, 0.9, 0.999, 1e-8, step)
     assert loss < 0.5 * first
     assert p.left.shape == (16, 24)
+
+
+@pytest.mark.parametrize("round_bf16", [False, True])
+def test_backward_from_given_output_gradient(orc, round_bf16):
+    """The backward from a given dL/dz4 equals the loss gradient when dL/dz4 is
+    the BCE gradient (sigmoid(z4) - y) / N of the loss's own logits, and it is
+    linear in dL/dz4 (scaling by a power of two scales every gradient exactly,
+    and a sum of two output gradients gives the sum of the two gradients when
+    nothing is rounded)."""
+    rng = np.random.default_rng(21)
+    B, H, W = 2, 9, 13
+    feat = rng.uniform(0, 1.5, (B, H, W, 4)).astype(np.float32)
+    label = (rng.uniform(size=(B, H, W)) < 0.6).astype(np.uint8)
+    prm = rand_params(rng)
+    _, z, g_loss = orc.lrnet(feat, prm, label, round_bf16=round_bf16, want_grad=True)
+    s = 1.0 / (1.0 + np.exp(-z.astype(np.float64)))
+    dz4 = ((s - label) / (B * H * W)).astype(np.float32)
+    g = orc.lrnet_backward(feat, dz4, prm, round_bf16=round_bf16)
+    assert np.array_equal(g, g_loss)
+    assert np.array_equal(orc.lrnet_backward(feat, 4 * dz4, prm, round_bf16=round_bf16), 4 * g)
+    if not round_bf16:
+        e = rng.standard_normal((B, H, W)).astype(np.float32) * 1e-3
+        ge = orc.lrnet_backward(feat, e, prm, round_bf16=False)
+        gs = orc.lrnet_backward(feat, dz4 + e, prm, round_bf16=False)
+        err = np.abs(gs.astype(np.float64) - g - ge)
+        assert err.max() <= 1e-5 * np.abs(g).max(), err.max()
