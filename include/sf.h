@@ -342,6 +342,19 @@ size_t sf_lrnet_workspace_bytes(int B, int H, int W, int train);
 /* logits [B][H][W] FP32 (output). */
 int sf_lrnet_forward(const float *params, const float *feat, int B, int H, int W, float *logits,
                      void *workspace, size_t ws_bytes, void *stream);
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): sf_lrnet_forward without a
+ * workspace argument.  Its only scratch (the packed weight fragments, 13,568
+ * bytes for any B, H, W) lives in a 16 KiB array of the library in each GPU's
+ * memory, held until the process ends; the call allocates nothing.  Every
+ * call on one GPU shares that array and overwrites it completely before
+ * reading it, so calls that overlap on one GPU (different streams, or
+ * different threads) race and must be ordered by the caller.  Same results
+ * and limits as sf_lrnet_forward (SF_EINVAL on NULL pointers or sizes beyond
+ * B <= 65535, B*H*W <= 2^30); SF_EHIP if the array's device address cannot
+ * be looked up. */
+int sf_lrnet_forward_noalloc(const float *params, const float *feat, int B, int H, int W,
+                             float *logits, void *stream);
 /* Learned mask of one map: valid = logit > 0 and x - d* >= 0 (a match pixel
  * outside the image can never pass the check); disp = d_sub where valid, else
  * -1.0f.  wta [H][W] int16 d*, dsub [H][W] FP32. */

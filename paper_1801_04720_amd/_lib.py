@@ -65,6 +65,7 @@ SIGNATURES = {
     "sf_lrnet_mask": (I, [P, P, P, I, I, P, P, P]),
     "sf_lrnet_grad": (I, [P, P, P, I, I, I, P, P, P, SZ, P]),
     "sf_lrnet_backward": (I, [P, P, P, I, I, I, P, P, SZ, P]),
+    "sf_lrnet_forward_noalloc": (I, [P, P, I, I, I, P, P]),
     "sf_mask_agreement": (I, [P, P, I, P, P]),
     "sf_lrnet_adam": (I, [P, P, P, P, I, F, F, F, F, F, F, P]),
     "sf_frame_run_learned": (I, [P, P, P, P, P, I, P, ct.POINTER(SfCamera), P, P, P, P, P, P, P, P,

@@ -23,6 +23,8 @@
 //   wgrad      dW[co][ci][tap] = sum_p gz[co](p) a[ci](p + tap - 1) on MFMA
 //              (K = pixels), per-block partials reduced in a fixed order
 //   adam       FP32 Adam step.
+#include <mutex>
+
 #include "lrnet_pack.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
@@ -793,6 +795,60 @@ extern "C" int sf_lrnet_forward(const float *params, const float *feat, int B, i
     SF_REQUIRE(logits, SF_EINVAL, "sf_lrnet_forward: NULL logits");
     return lrnet_forward(params, feat, B, H, W, logits, static_cast<uint8_t *>(workspace),
                          as_stream(stream));
+}
+
+// --- forward without allocation ----------------------------------------------
+// The fused inference needs only the packed weight fragments and biases as
+// scratch (lr_layout(.., false): 13,568 bytes, independent of B, H, W).  For
+// callers that cannot allocate, they live in a file-scope device array: each
+// GPU holds its own copy, whose device address is looked up once per device
+// (with that device current) and kept; host code never passes the array's
+// name itself to a kernel.
+constexpr size_t LR_SCRATCH_BYTES = 16384;
+static __device__ __align__(256) uint8_t scratch[LR_SCRATCH_BYTES];
+
+constexpr int LR_SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[LR_SCRATCH_MAX_DEVICES] = {};
+
+static int lr_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error("sf_lrnet_forward_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+        return SF_EHIP;
+    }
+    SF_REQUIRE(dev >= 0 && dev < LR_SCRATCH_MAX_DEVICES, SF_EUNSUPPORTED,
+               "sf_lrnet_forward_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("sf_lrnet_forward_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+            return SF_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SF_OK;
+}
+
+extern "C" int sf_lrnet_forward_noalloc(const float *params, const float *feat, int B, int H, int W,
+                                        float *logits, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(params && feat && logits, SF_EINVAL, "sf_lrnet_forward_noalloc: NULL pointer");
+    SF_REQUIRE(B > 0 && H > 0 && W > 0, SF_EINVAL, "sf_lrnet_forward_noalloc: B, H, W must be positive");
+    SF_REQUIRE(B <= 65535 && (long long)B * H * W <= (1LL << 30), SF_EINVAL,
+               "sf_lrnet_forward_noalloc: batch too large");
+    SF_REQUIRE(lr_layout(B, H, W, false).total <= LR_SCRATCH_BYTES, SF_ENOMEM,
+               "sf_lrnet_forward_noalloc: scratch smaller than the weight fragments");
+    void *scr = nullptr;
+    const int rc = lr_scratch(&scr);
+    if (rc) return rc;
+    return lrnet_forward(params, feat, B, H, W, logits, static_cast<uint8_t *>(scr), as_stream(stream));
 }
 
 extern "C" int sf_lrnet_mask(const float *logits, const int16_t *wta, const float *dsub, int H,

@@ -157,3 +157,6 @@ def test_network_and_judge_validation(L):
     expect(L.sf_lrnet_backward(FAKE, FAKE, FAKE, 1, 4, 4, FAKE, FAKE, 16, None), 4, "workspace")
     expect(L.sf_mask_agreement(FAKE, None, 10, FAKE, None), 1, "NULL")
     expect(L.sf_mask_agreement(FAKE, FAKE, 0, FAKE, None), 1, "positive")
+    expect(L.sf_lrnet_forward_noalloc(None, FAKE, 1, 4, 4, FAKE, None), 1, "NULL")
+    expect(L.sf_lrnet_forward_noalloc(FAKE, FAKE, 1, 0, 4, FAKE, None), 1, "positive")
+    expect(L.sf_lrnet_forward_noalloc(FAKE, FAKE, 70000, 4, 4, FAKE, None), 1, "too large")
