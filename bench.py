@@ -15,6 +15,7 @@ import argparse
 import ctypes as ct
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -182,29 +183,57 @@ def cpu_baseline(fr, D, runs=3):
     host thread; the median run gives the rate."""
     import oracle
 
-    times = []
-    for _ in range(runs):
-        t = time.perf_counter()
-        oracle.disparity(fr.t0.left, fr.t0.right, D)
-        times.append(time.perf_counter() - t)
+    # Pinned to one core of those this process may use (the oracle is single-threaded).
+    allowed = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else []
+    core = allowed[0] if allowed else None
+    if core is not None:
+        os.sched_setaffinity(0, {core})
+    try:
+        times = []
+        for _ in range(runs):
+            t = time.perf_counter()
+            oracle.disparity(fr.t0.left, fr.t0.right, D)
+            times.append(time.perf_counter() - t)
+    finally:
+        if core is not None:
+            os.sched_setaffinity(0, set(allowed))
     dt = sorted(times)[len(times) // 2]
     H, W = fr.t0.left.shape
     return {"value": H * W * D * 8 / dt / 1e9, "unit": "GCUPS", "cores": 1, "kind": "oracle",
             "sample": f"one {W}x{H} D={D} stereo pair (t0 of frame 0): census of both views, both "
                       f"cost volumes, both 8-path aggregations, WTA, sub-pixel, LR check; "
-                      f"single thread, median of {runs} runs ({', '.join(f'{x:.2f}' for x in times)} s)",
-            "seconds": dt, "runs_s": times, "cpu_model": _cpu_model(), "host_threads": os.cpu_count()}
+                      f"single thread pinned to core {core}, median of {runs} runs "
+                      f"({', '.join(f'{x:.2f}' for x in times)} s)",
+            "seconds": dt, "runs_s": times, "pinned_core": core, "cpu": _cpu_model(),
+            "host_threads": os.cpu_count(), "affinity_threads": len(allowed) or None}
 
 
 def _cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model string, family / model /
+    stepping numbers, clock, cache (a virtual machine may shorten the string)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    if info:
+                        break  # first processor only
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k in ("vendor_id", "model name", "cpu family", "model", "stepping", "microcode", "cpu MHz",
+                         "cache size") and k not in info:
+                    info[k] = v
     except OSError:
         pass
-    return None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "BIOS Model name", "Hypervisor vendor", "Virtualization type"):
+                info["lscpu " + k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info or None
 
 
 def _gen_pair(arg):
@@ -339,7 +368,7 @@ def bench_stream(args, dev):
     import torch
 
     from paper_1801_04720_amd import api, batch
-    from paper_1801_04720_amd.pipeline import FusedFrame
+    from paper_1801_04720_amd.pipeline import FusedFrame, JudgedLearnedStream
 
     H, W, D = 1024, 2048, 256
     n = args.frames
@@ -357,30 +386,36 @@ def bench_stream(args, dev):
     s = torch.cuda.current_stream()
 
     def run_stream(judge_every):
+        """judge_every > 0: the judged learned stream (JudgedLearnedStream: the plain
+        frame judges every judge_every-th frame and is delivered there; below the
+        agreement threshold the frames up to the next judge are plain frames);
+        0: the all-plain stream."""
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
-        agree = []
-        for i, f in enumerate(frames[:2]):  # warm-up, judge comparison included
-            out = (learned if judge_every else plain).run(*f)
-            if judge_every:
-                ref = plain.run(*f)
-                (out["valid0"] == ref["valid0"]).float().mean().item()
+        js = None
+        if judge_every:
+            js = JudgedLearnedStream(H, W, D, prm, judge_every=judge_every, threshold=args.fallback_threshold,
+                                     device=dev, learned=learned, plain=plain)
+        for f in frames[:2]:  # warm-up, a judged frame included
+            (js if judge_every else plain).run(*f)
+        if js is not None:
+            js.k, js.mode, js.history = 0, "learned", []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        modes = []
         for i, f in enumerate(frames):
             ev[i][0].record(s)
             if judge_every:
-                out = learned.run(*f)
-                if i % judge_every == 0:
-                    ref = plain.run(*f)
-                    # Read back after the stream ends: a host sync here would drain the queue.
-                    agree.append([(out[k] == ref[k]).float().mean() for k in ("valid0", "valid1")])
+                judged = js.k % judge_every == 0
+                js.run(*f)
+                modes.append("judged" if judged else js.mode)
             else:
                 plain.run(*f)
             ev[i][1].record(s)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         lat = np.array([a.elapsed_time(b) for a, b in ev])
-        return wall, lat, [[float(x.item()) for x in a] for a in agree]
+        agree = [[h[1], h[2]] for h in js.history] if js else []
+        return wall, lat, agree, modes
 
     def run_stream_from_host(judge_every):
         """Inputs start in pinned host memory and the scene flow (sf4 + valid) goes
@@ -433,8 +468,8 @@ def bench_stream(args, dev):
         lat = np.array([a.elapsed_time(b) for a, b in zip(t_in, t_out)])
         return wall, lat, [float(a.item()) for a in agree]
 
-    wl, ll, agree = run_stream(16)
-    wp, lp, _ = run_stream(0)
+    wl, ll, agree, modes = run_stream(16)
+    wp, lp, _, _ = run_stream(0)
     we, le, agree_e = run_stream_from_host(16)
 
     # Per-kernel times of the plain frame at this size, where the per-pixel
@@ -467,7 +502,8 @@ def bench_stream(args, dev):
         "ms_per_step": 1e3 * wl / n, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u16", "data": "synthetic (seeded piecewise-planar 2048x1024 frames, flow within 200 px)",
         "config": {"workload": f"{n} frames 2048x1024 D=256: learned frame (t0+t1 in one aggregation "
-                               "launch, network mask) with the plain frame as judge on every 16th"},
+                               "launch, network mask) with the plain frame as judge on every 16th and "
+                               "as fallback below the agreement threshold"},
         "learned_stream": {"fps": n / wl, "p50_ms": float(np.percentile(ll, 50)),
                            "p99_ms": float(np.percentile(ll, 99))},
         "plain_stream": {"fps": n / wp, "p50_ms": float(np.percentile(lp, 50)),
@@ -480,6 +516,12 @@ def bench_stream(args, dev):
         "judge_mask_agreement_mean": [float(np.mean([a[0] for a in agree])), float(np.mean([a[1] for a in agree]))],
         "judge_mask_agreement_min": [float(np.min([a[0] for a in agree])), float(np.min([a[1] for a in agree]))],
         "judged_frames": len(agree),
+        "fallback": {"threshold": args.fallback_threshold,
+                     "frames_judged": modes.count("judged"), "frames_learned": modes.count("learned"),
+                     "frames_plain_fallback": modes.count("plain"),
+                     "policy": "the plain frame judges every 16th frame and is delivered there; when the "
+                               "lower of its t0 / t1 mask agreements with the learned frame falls below the "
+                               "threshold, the frames up to the next judge are plain frames"},
         "plain_frame_kernels_2048x1024": kern,
         "tuning": {"learned_2views": batch.tuning_dict(t2), "plain_4views": batch.tuning_dict(t4)},
     }
@@ -769,6 +811,8 @@ def main():
                          "uneven batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); "
                          "stream: 2048x1024 D=256 frames, learned with a plain judge every 16th")
     ap.add_argument("--frames", type=int, default=240, help="frames in the 2048x1024 stream")
+    ap.add_argument("--fallback-threshold", type=float, default=0.99,
+                    help="stream: mask agreement below which the judged stream falls back to plain frames")
     ap.add_argument("--pairs", type=int, default=64, help="pairs in the uneven batch")
     ap.add_argument("--mem-budget-gb", type=float, default=128.0,
                     help="workspace per wave of the uneven batch")

@@ -128,11 +128,14 @@ class JudgedLearnedStream:
     `history` holds (frame index, agreement t0, agreement t1, mode chosen)."""
 
     def __init__(self, H: int, W: int, D: int, params, judge_every: int = 16, threshold: float = 0.99,
-                 tuning_learned=None, tuning_plain=None, device="cuda:0", **kw):
+                 tuning_learned=None, tuning_plain=None, device="cuda:0", learned=None, plain=None, **kw):
+        """learned / plain: existing FusedFrame objects of this size to reuse (their
+        plans and buffers); otherwise both are created here."""
         if judge_every < 1:
             raise ValueError("judge_every must be >= 1")
-        self.learned = FusedFrame(H, W, D, learned_params=params, tuning=tuning_learned, device=device, **kw)
-        self.plain = FusedFrame(H, W, D, tuning=tuning_plain, device=device, **kw)
+        self.learned = learned or FusedFrame(H, W, D, learned_params=params, tuning=tuning_learned, device=device,
+                                             **kw)
+        self.plain = plain or FusedFrame(H, W, D, tuning=tuning_plain, device=device, **kw)
         self.judge_every, self.threshold = judge_every, float(threshold)
         self.count = torch.zeros(2, dtype=torch.int32, device=device)
         self.count_host = torch.zeros(2, dtype=torch.int32).pin_memory()

@@ -213,3 +213,25 @@ def test_checkpoint_resume_bit_exact():
     lb = float(b.step(feat, label).item())
     assert la == lb
     assert np.array_equal(host(a.params), host(b.params))
+
+
+def test_training_resume_bit_exact(tmp_path):
+    """train_lrnet: a run stopped at a checkpoint and resumed from it ends with
+    the same weights and moments as the uninterrupted run (the checkpoint holds
+    the Adam state, the step, the seed and the crop sampler's generator state)."""
+    from paper_1801_04720_amd import train_lrnet as tl
+
+    say("lrnet training resume")
+    cfg = {"t0": 2, "t1": 1, "big": 0, "val_t0": 1, "val_t1": 1, "val_big": 0, "steps": 12, "batch": 2,
+           "crop": [64, 128], "lr": 3e-3, "seed": 5, "workers": 2, "ckpt": None, "ckpt_every": 0}
+    full, ev = tl.train(dict(cfg), log=say)
+    assert ev["val"]["t0"]["maps"] == 1 and ev["val"]["t1"]["maps"] == 1
+    ck = str(tmp_path / "ck.npz")
+    part, _ = tl.train(dict(cfg, ckpt=ck, ckpt_every=5), log=say, stop_after=7)
+    with np.load(ck, allow_pickle=False) as z:
+        assert int(z["next_step"]) == 5 and int(z["seed"]) == 5
+    resumed, _ = tl.train(dict(cfg, ckpt=ck, ckpt_every=5), log=say, resume=ck)
+    a, b = full.state(), resumed.state()
+    assert a["step"] == b["step"] == 12
+    for k in ("params", "m", "v"):
+        assert np.array_equal(a[k], b[k]), k
