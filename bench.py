@@ -528,6 +528,55 @@ def bench_stream(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_lrnet(args, dev):
+    """The fused network inference alone (lrnet_fused_kernel, weights packed by
+    their own launch) on the two left maps of the 1242x375 D=128 frame: kernel
+    time from HIP events on the launch stream, useful FLOP rate (10,656 FLOP per
+    pixel) against the dense BF16 MFMA peak."""
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import _lib, api, lrnet, synth
+
+    H, W, D = 375, 1242, 128
+    fr = synth.frame_1242x375(0)
+    feats = []
+    for L, R in ((fr.t0.left, fr.t0.right), (fr.t1.left, fr.t1.right)):
+        Lt, Rt = torch.from_numpy(L).to(dev), torch.from_numpy(R).to(dev)
+        cl, cr = api.census(Lt), api.census(Rt)
+        S = api.sgm_aggregate(api.cost(cl, cr, D, False), 10, 120)
+        feats.append(api.wta_lr(S, None, Lt, 120, 1, want_feat=True)["feat"])
+    feat = torch.stack(feats).contiguous()
+    with np.load(args.lrnet, allow_pickle=False) as z:
+        prm = torch.from_numpy(z["params"].astype(np.float32)).to(dev)
+    logits = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+    ws = torch.empty(lrnet.workspace_bytes(2, H, W, False), dtype=torch.uint8, device=dev)
+    for _ in range(args.warmup):
+        lrnet.forward(prm, feat, logits, ws)
+    lib = _lib.lib()
+    torch.cuda.synchronize()
+    _lib.check(lib.sf_prof_enable(4 * max(args.steps, 1)))
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lrnet.forward(prm, feat, logits, ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.sf_prof_disable()
+    tot, n = kernel_ms(lib, "lrnet_fused")
+    ms = tot / max(n, 1)
+    flop = 2 * H * W * 10656.0
+    peak = 2.5e15
+    res = {"metric": "learned LR stand-in inference: fused 4-layer network, two 1242x375 maps",
+           "value": flop / (ms * 1e-3) / 1e12, "unit": "TFLOP/s (useful)", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * wall / max(args.steps, 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic (features of the seeded frame)",
+           "config": {"workload": "fused network inference on 2 maps of 1242x375 (features of frame 0)"},
+           "kernel_ms": ms, "timed_launches": n, "flop_per_launch": flop,
+           "roofline": {"bound": "mfma", "achieved": flop / (ms * 1e-3) / 1e12, "peak": peak / 1e12,
+                        "unit": "TFLOP/s", "frac": flop / (ms * 1e-3) / peak}}
+    print(json.dumps(res), flush=True)
+
+
 def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     """Learned frame (right views skipped, network mask): fps, speed-up over the
     plain frame, and agreement of its masks with the plain LR check on this frame."""
@@ -806,10 +855,11 @@ def main():
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
                                                     "lrnet_1242x375.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
-    ap.add_argument("--workload", default="frame", choices=["frame", "batch", "stream"],
+    ap.add_argument("--workload", default="frame", choices=["frame", "batch", "stream", "lrnet"],
                     help="frame: the 1242x375 D=128 scene-flow frame (default); batch: the "
                          "uneven batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); "
-                         "stream: 2048x1024 D=256 frames, learned with a plain judge every 16th")
+                         "stream: 2048x1024 D=256 frames, learned with a plain judge every 16th; "
+                         "lrnet: the fused network inference alone on two 1242x375 maps")
     ap.add_argument("--frames", type=int, default=240, help="frames in the 2048x1024 stream")
     ap.add_argument("--fallback-threshold", type=float, default=0.99,
                     help="stream: mask agreement below which the judged stream falls back to plain frames")
@@ -863,6 +913,8 @@ def main():
         return bench_batch(args, dev)
     if args.workload == "stream":
         return bench_stream(args, dev)
+    if args.workload == "lrnet":
+        return bench_lrnet(args, dev)
     H, W, D = 375, 1242, 128
     fr = synth.frame_1242x375(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731

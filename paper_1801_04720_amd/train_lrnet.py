@@ -233,10 +233,18 @@ def train(cfg: dict, dev="cuda:0", log=print, resume: str | None = None, stop_af
     steps = cfg["steps"]
     hist = []
     t1 = time.time()
+    kinds = sorted(set(train_set.kind))
+    by_kind = [[k for k in range(nmaps) if train_set.kind[k] == kd] for kd in kinds]
     for step in range(start, steps):
         # Step decay of the learning rate: x0.3 at 60 % of the steps, x0.03 at 85 %.
         tr.lr = cfg["lr"] * (1.0 if step < int(0.6 * steps) else (0.3 if step < int(0.85 * steps) else 0.03))
-        idx = torch.randint(0, nmaps, (B,), generator=g)
+        if cfg.get("balance"):
+            # Each kind of map equally often, then a map of that kind.
+            kk = torch.randint(0, len(kinds), (B,), generator=g)
+            rr = torch.rand((B,), generator=g)
+            idx = [by_kind[int(kk[b])][int(rr[b] * len(by_kind[int(kk[b])]))] for b in range(B)]
+        else:
+            idx = torch.randint(0, nmaps, (B,), generator=g)
         u = torch.rand((B, 2), generator=g)
         for b in range(B):
             i = int(idx[b])
@@ -287,6 +295,8 @@ def main():
     ap.add_argument("--ckpt", default=None, help="checkpoint file (written every --ckpt-every steps)")
     ap.add_argument("--ckpt-every", type=int, default=2000)
     ap.add_argument("--resume", default=None, help="continue the run saved in this checkpoint")
+    ap.add_argument("--balance", action="store_true",
+                    help="sample the kinds of maps (t0, t1, big) equally often instead of in proportion")
     ap.add_argument("--calibrate", type=int, default=0,
                     help="after training, shift the output bias to the agreement-maximising threshold "
                          "found on this many training maps of each kind (0: no shift)")
@@ -298,7 +308,7 @@ def main():
     cfg = {"t0": args.t0, "t1": args.t1, "big": args.big, "val_t0": args.val_t0, "val_t1": args.val_t1,
            "val_big": args.val_big, "steps": args.steps, "batch": args.batch, "crop": list(args.crop),
            "lr": args.lr, "seed": args.seed, "workers": args.workers, "ckpt": args.ckpt,
-           "ckpt_every": args.ckpt_every, "calibrate": args.calibrate}
+           "ckpt_every": args.ckpt_every, "calibrate": args.calibrate, "balance": bool(args.balance)}
     log = lambda s: print(s, flush=True)  # noqa: E731
     if args.eval_only:
         with np.load(args.eval_only, allow_pickle=False) as z:
