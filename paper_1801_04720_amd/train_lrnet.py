@@ -159,37 +159,37 @@ def evaluate(params, ms: MapSet, dev="cuda:0"):
 
 
 def calibrate_bias(tr, ms: MapSet, n: int, dev="cuda:0") -> float:
-    """Shift the output bias b4 by the logit threshold that maximises the mask's
-    agreement with the LR check on the first n maps of each kind in the
-    training set; the mask rule itself stays logit > 0.  (The mask also needs
-    x - d* >= 0, which every pixel of these maps meets: a match outside the
-    image costs the maximum, so WTA never picks it.)  Returns the threshold."""
-    lg, lb = [], []
+    """Shift the output bias b4 by the logit threshold that maximises the lowest
+    of the per-kind agreements (t0, t1, big) of the mask with the LR check, on
+    the first n training maps of each kind; the mask rule itself stays
+    logit > 0.  (The mask also needs x - d* >= 0, which every pixel of these
+    maps meets: a match outside the image costs the maximum, so WTA never picks
+    it.)  Thresholds are searched on a grid of 1/256 in [-4, 4].  Returns the
+    threshold."""
+    edges = torch.arange(-1024, 1025, device=dev, dtype=torch.float64) / 256.0
+    per_kind = {}
     seen = {}
     for k in range(len(ms)):
-        if seen.get(ms.kind[k], 0) >= n:
+        kd = ms.kind[k]
+        if seen.get(kd, 0) >= n:
             continue
-        seen[ms.kind[k]] = seen.get(ms.kind[k], 0) + 1
-        logits = lrnet.forward(tr.params, ms.feats[k][None])[0]
-        lg.append(logits.reshape(-1))
-        lb.append(ms.labels[k].reshape(-1))
-    z = torch.cat(lg).double()
-    y = torch.cat(lb).bool()
-    order = torch.argsort(z)
-    zs, ys = z[order], y[order].double()
-    # Threshold between zs[i-1] and zs[i]: pixels i.. are kept.  Errors = valid
-    # pixels dropped (ys = 1 below i) + invalid pixels kept (ys = 0 from i on).
-    pos_below = torch.cat([torch.zeros(1, dtype=torch.float64, device=z.device), torch.cumsum(ys, 0)])
-    neg_above = (1 - ys).sum() - torch.cat([torch.zeros(1, dtype=torch.float64, device=z.device),
-                                            torch.cumsum(1 - ys, 0)])
-    err = pos_below + neg_above
-    i = int(torch.argmin(err))
-    if i == 0:
-        thr = float(zs[0]) - 1e-3
-    elif i == zs.numel():
-        thr = float(zs[-1]) + 1e-3
-    else:
-        thr = 0.5 * (float(zs[i - 1]) + float(zs[i]))
+        seen[kd] = seen.get(kd, 0) + 1
+        z = lrnet.forward(tr.params, ms.feats[k][None])[0].reshape(-1).double()
+        y = ms.labels[k].reshape(-1).bool()
+        # Errors at threshold e: valid pixels with z <= e plus invalid pixels with z > e.
+        pos_le = torch.searchsorted(torch.sort(z[y]).values, edges, right=True).double()
+        neg_sorted = torch.sort(z[~y]).values
+        neg_gt = neg_sorted.numel() - torch.searchsorted(neg_sorted, edges, right=True).double()
+        acc = per_kind.setdefault(kd, [torch.zeros_like(edges), 0])
+        acc[0] += pos_le + neg_gt
+        acc[1] += z.numel()
+    agree = torch.stack([1.0 - e / cnt for e, cnt in per_kind.values()])
+    worst = agree.min(dim=0).values
+    best = float(worst.max())
+    # The threshold closest to 0 among those reaching the best lowest agreement.
+    cand = torch.nonzero(worst >= best).reshape(-1)
+    i = int(cand[torch.argmin(edges[cand].abs())])
+    thr = float(edges[i])
     tr.params[5376] -= thr
     return thr
 
@@ -211,7 +211,12 @@ def train(cfg: dict, dev="cuda:0", log=print, resume: str | None = None, stop_af
                          keep_gt=True, log=log)
     t_data = time.time() - t0
     log(f"labelled {len(train_set)} training and {len(val_set)} validation maps in {t_data:.1f} s")
-    tr = lrnet.Trainer(lrnet.init_params(cfg["seed"]), lr=cfg["lr"], device=dev)
+    init = lrnet.init_params(cfg["seed"])
+    if cfg.get("init"):
+        with np.load(cfg["init"], allow_pickle=False) as z:
+            init = z["params"].astype(np.float32)
+        log(f"initial weights from {cfg['init']}")
+    tr = lrnet.Trainer(init, lr=cfg["lr"], device=dev)
     g = torch.Generator(device="cpu").manual_seed(cfg["seed"])
     start = 0
     if resume:
@@ -295,6 +300,7 @@ def main():
     ap.add_argument("--ckpt", default=None, help="checkpoint file (written every --ckpt-every steps)")
     ap.add_argument("--ckpt-every", type=int, default=2000)
     ap.add_argument("--resume", default=None, help="continue the run saved in this checkpoint")
+    ap.add_argument("--init", default=None, help="start from the weights of this .npz (fine-tuning)")
     ap.add_argument("--balance", action="store_true",
                     help="sample the kinds of maps (t0, t1, big) equally often instead of in proportion")
     ap.add_argument("--calibrate", type=int, default=0,
@@ -308,7 +314,8 @@ def main():
     cfg = {"t0": args.t0, "t1": args.t1, "big": args.big, "val_t0": args.val_t0, "val_t1": args.val_t1,
            "val_big": args.val_big, "steps": args.steps, "batch": args.batch, "crop": list(args.crop),
            "lr": args.lr, "seed": args.seed, "workers": args.workers, "ckpt": args.ckpt,
-           "ckpt_every": args.ckpt_every, "calibrate": args.calibrate, "balance": bool(args.balance)}
+           "ckpt_every": args.ckpt_every, "calibrate": args.calibrate, "balance": bool(args.balance),
+           "init": args.init}
     log = lambda s: print(s, flush=True)  # noqa: E731
     if args.eval_only:
         with np.load(args.eval_only, allow_pickle=False) as z:
