@@ -512,11 +512,22 @@ __global__ void pack_fused_kernel(const float *__restrict__ prm, uint4 *__restri
     lrnet_pack_lane(prm, frag, fl, blockIdx.x, threadIdx.x & 63);
 }
 
+// Pixels per plane of a 16-channel activation array of np pixels: the least
+// count >= np that is 16 mod 32, so that planes start 128 bytes apart modulo
+// the 256 bytes that the LDS banks span.
+__host__ __device__ constexpr int plane_px(int np) { return ((np + 15) & ~31) + 16; }
+
 // Offset (in BF16 elements) of channels 4 kg .. 4 kg + 3 of pixel p in a
-// 16-channel activation array.  A pixel takes 32 bytes, so the 8-byte reads of
-// one channel block by 16 consecutive pixels would meet in the same LDS banks;
-// the four blocks are XOR-swizzled by bits 2..3 of p, which spreads them.
-__device__ __forceinline__ int act_off(int p, int kg) { return p * 16 + 4 * (kg ^ ((p >> 2) & 3)); }
+// 16-channel activation array of np pixels, stored as four planes of channel
+// blocks (plane kg holds channels 4 kg .. 4 kg + 3 of every pixel, 8 bytes per
+// pixel).  The 8-byte accesses of one channel block by 16 consecutive pixels
+// are 128 contiguous bytes, two lane groups on neighbouring planes fall on
+// disjoint banks (plane_px), and the nine taps of a 3x3 window are constant
+// offsets from one base address.
+__device__ __forceinline__ int act_off(int p, int kg, int np) { return (kg * plane_px(np) + p) * 4; }
+
+// ReLU with the maxNum rule: x for x > 0, else 0, and 0 for a NaN.
+__device__ __forceinline__ float relu_mfma(float x) { return __builtin_fmaxf(x, 0.0f); }
 
 __device__ __forceinline__ bf16x8 join8(uint2 lo, uint2 hi)
 {
@@ -524,7 +535,7 @@ __device__ __forceinline__ bf16x8 join8(uint2 lo, uint2 hi)
 }
 
 // One 3x3 MFMA layer over a region: input sIn [hi][wi][C] (bf16; C = 16 arrays
-// swizzled by act_off), output sOut [hi-2][wi-2][16] (swizzled); (gy0, gx0) =
+// in channel-block planes, act_off), output sOut [hi-2][wi-2][16] (planes); (gy0, gx0) =
 // image coordinates of the output region's first pixel; bias = the biases of
 // output channels 4 kg .. 4 kg + 3; frag = the layer's first weight slot.
 template <int C>
@@ -550,11 +561,12 @@ __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi,
         // All LDS reads of the group are issued before the MFMA chain uses any.
         bf16x8 b32[NQ];
         if (C == 16) {
+            const uint16_t *base = sIn + act_off(p0, kg, hi * wi);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                b32[q] = join8(*reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(2 * q, wi), kg)),
-                               *reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(2 * q + 1, wi), kg)));
-            b32[4] = join8(*reinterpret_cast<const uint2 *>(sIn + act_off(p0 + tap_off(8, wi), kg)), zero2);
+                b32[q] = join8(*reinterpret_cast<const uint2 *>(base + 4 * tap_off(fused_tap(q, 0), wi)),
+                               *reinterpret_cast<const uint2 *>(base + 4 * tap_off(fused_tap(q, 1), wi)));
+            b32[4] = join8(*reinterpret_cast<const uint2 *>(base + 4 * tap_off(8, wi)), zero2);
         } else {
             b32[0] = join8(*reinterpret_cast<const uint2 *>(sIn + (p0 + tap_off(kg, wi)) * 4),
                            *reinterpret_cast<const uint2 *>(sIn + (p0 + tap_off(kg + 4, wi)) * 4));
@@ -567,19 +579,21 @@ __device__ __forceinline__ void fused_layer(const uint16_t *sIn, int hi, int wi,
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w32[q], b32[q], acc, 0, 0, 0);
         if (mo >= nout) continue;
-        bool inside = interior;
-        if (!interior) {
-            const int gy = gy0 + oy, gx = gx0 + ox;
-            inside = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
-        }
         float v[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = (acc[i] > 0.0f && inside) ? acc[i] : 0.0f;  // ReLU (NaN -> 0), padding
-        *reinterpret_cast<uint2 *>(sOut + act_off(mo, kg)) = make_uint2(bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3]));
+        for (int i = 0; i < 4; ++i) v[i] = relu_mfma(acc[i]);
+        if (!interior) {  // uniform over the block
+            const int gy = gy0 + oy, gx = gx0 + ox;
+            if (!((unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W)) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = 0.0f;  // zero padding outside the image
+            }
+        }
+        *reinterpret_cast<uint2 *>(sOut + act_off(mo, kg, nout)) = make_uint2(bf16x2_bits(v[0], v[1]), bf16x2_bits(v[2], v[3]));
     }
 }
 
-__global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__restrict__ frag,
+__global__ __launch_bounds__(64 * FT_NW) __attribute__((amdgpu_waves_per_eu(8, 8))) void lrnet_fused_kernel(const uint4 *__restrict__ frag,
                                                                  const float *__restrict__ fl,
                                                                  const float4 *__restrict__ feat,
                                                                  int H, int W, float *__restrict__ logits,
@@ -590,10 +604,11 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
     constexpr int H2 = FT_H + 4, W2 = FT_W + 4;   // a2
     constexpr int H3 = FT_H + 2, W3 = FT_W + 2;   // a3 (aliases a1)
     constexpr int N3 = H3 * W3;                   // a3 pixels; P (9 x N3 FP32) aliases a2
-    static_assert(9 * N3 * 4 <= H2 * W2 * 16 * 2, "tap sums must fit the a2 buffer");
+    static_assert(9 * N3 * 4 <= plane_px(H2 * W2) * 16 * 2, "tap sums must fit the a2 buffer");
     __shared__ __align__(16) uint16_t sF[FH * FW * 4];
-    __shared__ __align__(16) uint16_t sA1[H1 * W1 * 16];
-    __shared__ __align__(16) uint16_t sA2[H2 * W2 * 16];
+    constexpr int NA1 = plane_px(H1 * W1) > plane_px(N3) ? plane_px(H1 * W1) : plane_px(N3);
+    __shared__ __align__(16) uint16_t sA1[NA1 * 16];           // a1, then a3
+    __shared__ __align__(16) uint16_t sA2[plane_px(H2 * W2) * 16];
     __shared__ __align__(16) uint4 sW[FP_FRAGS];  // weight fragments [slot][lane], staged from global
     const int b = blockIdx.z;
     const int x0 = blockIdx.x * FT_W, y0 = blockIdx.y * FT_H;
@@ -624,7 +639,7 @@ __global__ __launch_bounds__(64 * FT_NW) void lrnet_fused_kernel(const uint4 *__
     for (int g = wave; g < (N3 + 15) / 16; g += FT_NW) {
         const int p = g * 16 + n;
         const int pc = p < N3 ? p : N3 - 1;
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(sA1 + act_off(pc, kg));
+        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(sA1 + act_off(pc, kg, N3));
         const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w4, a, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         if (p < N3) {
 #pragma unroll
@@ -766,9 +781,11 @@ int lrnet_forward(const float *params, const float *feat, int B, int H, int W, f
     const LrLayout L = lr_layout(B, H, W, false);
     uint4 *frag = reinterpret_cast<uint4 *>(ws + L.frag);
     float *fl = reinterpret_cast<float *>(ws + L.fl);
-    ProfScope prof("lrnet_fused", st);
-    if (!prepacked)
+    if (!prepacked) {
+        ProfScope prof("lrnet_pack", st);
         hipLaunchKernelGGL(pack_fused_kernel, dim3(FP_NSLOT), dim3(64), 0, st, params, frag, fl);
+    }
+    ProfScope prof("lrnet_fused", st);  // the fused inference launch alone
     dim3 g((W + FT_W - 1) / FT_W, (H + FT_H - 1) / FT_H, B);
     hipLaunchKernelGGL(lrnet_fused_kernel, g, dim3(64 * FT_NW), 0, st, frag, fl,
                        reinterpret_cast<const float4 *>(feat), H, W, logits, mo);

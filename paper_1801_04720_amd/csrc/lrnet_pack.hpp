@@ -21,6 +21,16 @@ constexpr int FP_L1 = 0, FP_L2 = 2, FP_L3 = 7, FP_L4 = 12, FP_NSLOT = 13;
 constexpr int FP_FRAGS = FP_NSLOT * 64;
 constexpr int FP_B1 = 0, FP_B2 = 16, FP_B3 = 32, FP_B4 = 48, FP_FLOATS = 49;
 
+// Taps (row-major over the 3x3 window) that K = 32 MFMA q (0..3) of a
+// 16-channel layer pairs, hi = 0 / 1: (0, 1), (3, 4), (6, 7), (2, 5); tap 8
+// goes with zeros in MFMA 4.  Each pair is two pixels a constant distance
+// apart, so one two-address LDS read fetches both channel blocks into
+// consecutive registers, the order the MFMA operand needs.
+__host__ __device__ constexpr int fused_tap(int q, int hi)
+{
+    return q == 3 ? (hi ? 5 : 2) : 3 * q + hi;
+}
+
 // FP32 -> BF16 bits, round to nearest even (NaN kept quiet).
 __device__ __forceinline__ uint16_t bf16_bits(float f)
 {
@@ -49,10 +59,10 @@ __device__ __forceinline__ void lrnet_pack_lane(const float *__restrict__ prm, u
             k = OFF_W1 + (n * 4 + i) * 9 + kg + 4 * hi;
         } else if (slot == FP_L1 + 1) {  // layer 1, tap 8 (lane group 0 only)
             if (kg == 0 && !hi) k = OFF_W1 + (n * 4 + i) * 9 + 8;
-        } else if (slot < FP_L4) {  // layers 2, 3: taps 2q, 2q + 1 (q < 4) or tap 8, channel 4 kg + i
+        } else if (slot < FP_L4) {  // layers 2, 3: taps fused_tap(q, 0 / 1) (q < 4) or tap 8, channel 4 kg + i
             const int q = (slot - FP_L2) % 5;
             const int off = slot < FP_L3 ? OFF_W2 : OFF_W3;
-            if (q < 4) k = off + (n * 16 + 4 * kg + i) * 9 + 2 * q + hi;
+            if (q < 4) k = off + (n * 16 + 4 * kg + i) * 9 + fused_tap(q, hi);
             else if (!hi) k = off + (n * 16 + 4 * kg + i) * 9 + 8;
         } else if (n < 9 && !hi) {  // layer 4: row n = tap n, input channel 4 kg + i
             k = OFF_W4 + (4 * kg + i) * 9 + n;

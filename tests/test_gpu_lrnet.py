@@ -47,6 +47,24 @@ def test_forward_exact_on_dyadic_grid(orc, B, H, W):
     assert np.array_equal(got, ref)
 
 
+def test_forward_nonfinite_features(orc):
+    """NaN and infinite features: the oracle's rules (ReLU maps a NaN to 0, a
+    zero weight times an infinity is a NaN, opposite infinities sum to a NaN)
+    hold on the GPU; the other logits stay exact on the dyadic grid."""
+    say("lrnet forward, non-finite features")
+    rng = np.random.default_rng(77)
+    B, H, W = 2, 19, 45
+    feat, prm = dyadic_setup(rng, B, H, W)
+    feat[0, 3, 5, 1] = np.nan
+    feat[0, 10, 20, 2] = np.inf
+    feat[1, 15, 30, 0] = -np.inf
+    feat[1, 0, 44, 3] = np.inf
+    got = host(lrnet.forward(dev(prm), dev(feat)))
+    _, ref, _ = orc.lrnet(feat, prm)
+    assert not np.isfinite(ref).all()
+    assert np.array_equal(got, ref, equal_nan=True)
+
+
 def _trained():
     import os
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
