@@ -577,6 +577,60 @@ def bench_lrnet(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_agg(args, dev):
+    """One left-base view of the 1242x375 D=128 frame: cost volume + eight-path
+    aggregation (sf_cost, sf_sgm_aggregate) against the aggregation that computes
+    the Hamming costs from the census images inside the path walk
+    (sf_sgm_aggregate_census).  Per-launch times from HIP events on the launch
+    stream; value = cell updates per second of the census-mode aggregation."""
+    import numpy as np
+    import torch
+
+    from paper_1801_04720_amd import _lib, api, synth
+
+    H, W, D = 375, 1242, 128
+    fr = synth.frame_1242x375(0)
+    L = torch.from_numpy(np.ascontiguousarray(fr.t0.left)).to(dev)
+    R = torch.from_numpy(np.ascontiguousarray(fr.t0.right)).to(dev)
+    cl, cr = api.census(L), api.census(R)
+    C = api.cost(cl, cr, D, False)
+    S1 = torch.empty((H, W, D), dtype=torch.int16, device=dev)
+    S2 = torch.empty_like(S1)
+    ws = torch.empty(api.sgm_workspace_bytes(H, W, D), dtype=torch.uint8, device=dev)
+    lib = _lib.lib()
+    res = {}
+    for name, fn in (("volume", lambda: (api.cost(cl, cr, D, False, out=C),
+                                         api.sgm_aggregate(C, 10, 120, out=S1, workspace=ws))),
+                     ("census", lambda: api.sgm_aggregate_census(cl, cr, D, False, 10, 120, out=S2,
+                                                                 workspace=ws))):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        _lib.check(lib.sf_prof_enable(8 * max(args.steps, 1)))
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        lib.sf_prof_disable()
+        r = {}
+        for k in ("cost", "sgm_paths", "slab_sum"):
+            tot, n = kernel_ms(lib, k)
+            if n:
+                r[k + "_ms"] = tot / n
+        r["total_ms"] = sum(r.values())
+        res[name] = r
+    if not torch.equal(S1, S2):
+        raise SystemExit("census-mode aggregation differs from the cost-volume path")
+    cells = H * W * D * 8
+    ms = res["census"]["sgm_paths_ms"]
+    out = {"metric": "eight-path aggregation of one 1242x375 D=128 view with costs from the census images",
+           "value": cells / (ms * 1e-3) / 1e9, "unit": "G cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u16", "data": "synthetic (left view of the seeded frame)",
+           "config": {"workload": "one view 1242x375 D=128, P1=10, P2=120, 8 paths"},
+           "legs": res}
+    print(json.dumps(out), flush=True)
+
+
 def learned_leg(args, plain_pipe, inputs, H, W, D, ms_plain, dev):
     """Learned frame (right views skipped, network mask): fps, speed-up over the
     plain frame, and agreement of its masks with the plain LR check on this frame."""
@@ -855,7 +909,7 @@ def main():
     ap.add_argument("--lrnet", default=os.path.join(ROOT, "paper_1801_04720_amd", "data",
                                                     "lrnet_1242x375.npz"),
                     help="trained parameters of the learned LR stand-in (.npz)")
-    ap.add_argument("--workload", default="frame", choices=["frame", "batch", "stream", "lrnet"],
+    ap.add_argument("--workload", default="frame", choices=["frame", "batch", "stream", "lrnet", "agg"],
                     help="frame: the 1242x375 D=128 scene-flow frame (default); batch: the "
                          "uneven batch of 64 pairs (640x480/64, 1242x375/128, 1920x1080/256); "
                          "stream: 2048x1024 D=256 frames, learned with a plain judge every 16th; "
@@ -915,6 +969,8 @@ def main():
         return bench_stream(args, dev)
     if args.workload == "lrnet":
         return bench_lrnet(args, dev)
+    if args.workload == "agg":
+        return bench_agg(args, dev)
     H, W, D = 375, 1242, 128
     fr = synth.frame_1242x375(0)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731

@@ -95,6 +95,18 @@ int sf_sgm_set_epilogue(int mode);
 int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1, int P2,
                      uint32_t path_mask, uint16_t *S, void *workspace, size_t ws_bytes,
                      void *stream);
+/* The same aggregation with the matching cost computed inside the path walk
+ * from the two census images (Sec. 3.1 paths; cost as sf_cost: the Hamming
+ * distance of the base pixel's census to the match pixel's, x - d for a left
+ * base, x + d for a right base, SF_CMAX where the match pixel is outside the
+ * image), so no cost volume is read or written.  S equals
+ * sf_cost(cen_base, cen_match, ...) followed by sf_sgm_aggregate.
+ *   cen_base, cen_match [H][W] uint64 (as sf_census writes them)
+ *   base_is_right 0 or 1; other arguments, limits and errors as sf_sgm_aggregate
+ *   (SF_EINVAL also for a NULL census or base_is_right outside {0, 1}). */
+int sf_sgm_aggregate_census(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W, int D,
+                            int base_is_right, int P1, int P2, uint32_t path_mask, uint16_t *S,
+                            void *workspace, size_t ws_bytes, void *stream);
 /* Intensity-adaptive variant of the cited SGM method: the large-jump penalty at
  * p is taken from the base image along the path,
  *   P2(p, r) = P2                          if g = |I(p) - I(p - r)| = 0

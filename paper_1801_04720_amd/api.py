@@ -79,6 +79,23 @@ def sgm_aggregate(cost_vol, P1: int, P2: int, path_mask: int = 0xFF, out=None, w
     return out
 
 
+def sgm_aggregate_census(cen_base, cen_match, D: int, base_is_right: bool, P1: int, P2: int,
+                         path_mask: int = 0xFF, out=None, workspace=None, stream=None):
+    """Aggregated costs S [H][W][D] with the Hamming costs computed inside the
+    aggregation from the two census images (no cost volume); equal to
+    sgm_aggregate(cost(cen_base, cen_match, D, base_is_right), P1, P2, path_mask)."""
+    H, W = cen_base.shape
+    if out is None:
+        out = torch.empty((H, W, D), dtype=torch.int16, device=cen_base.device)
+    if workspace is None:
+        workspace = torch.empty(sgm_workspace_bytes(H, W, D), dtype=torch.uint8,
+                                device=cen_base.device)
+    check(lib().sf_sgm_aggregate_census(_ptr(cen_base), _ptr(cen_match), H, W, D, int(base_is_right), P1,
+                                        P2, path_mask, _ptr(out), _ptr(workspace), workspace.numel(),
+                                        _stream(stream)))
+    return out
+
+
 def wta_lr(S_left, S_right=None, img_left=None, P2: int = 120, lr_tol: int = 1, want_feat=False,
            out=None, stream=None):
     """WTA + sub-pixel + LR check (+ features).

@@ -51,7 +51,9 @@ __constant__ int c_dir[8][2] = {{+1, 0}, {-1, 0}, {0, +1}, {0, -1},
 struct PathTable {
     int ndir;
     int dir[8];
-    int off[9];        // chain-index prefix sums
+    int n[8];          // chains of each selected direction
+    int off[9];        // prefix sums of the chain counts rounded up to whole blocks, so
+                       // that every block (and wave) walks chains of one direction
 };
 
 // Start pixel and length of chain l of direction r.
@@ -311,18 +313,87 @@ __device__ __forceinline__ void unpack_pk(const CostPk<K> &r, int j, uint32_t (&
     }
 }
 
+// Census mode (no cost volume): the lane computes its K costs of a pixel from
+// the base pixel's census word and the K match words, C = popcount(base ^
+// match), SF_CMAX where the match pixel lies outside the image.  CEN = 1: left
+// base, match pixel x - d; CEN = 2: right base, match pixel x + d.  The match
+// words of relative disparity e = 0 .. K-1 are K consecutive words of the row,
+// fetched as K/2 16-byte loads: load q holds e = 2q, 2q + 1 (right base,
+// ascending x) or e = 2q + 1, 2q (left base, descending x).  A left-base load
+// that would start one word before the array (x - d = 0 on row 0 for e = 2q)
+// starts at the array instead (the buffer's range check would drop both words
+// otherwise), so e = 2q then sits in the first half; that happens only where
+// some lane has a match pixel outside the image, the slow path below.
+template <int K>
+struct CenRaw {
+    uint32_t b[2];      // base census word (low, high)
+    uint32_t m[2 * K];  // match words as loaded, 4 per 16-byte load
+    int lim;            // the match pixel of relative disparity e is inside iff e <= lim
+    int row0;           // the pixel is on row 0 (left base: loads may have been moved)
+};
+
+// Words of relative disparity e in the load order (no moved load).
+template <int K, int CEN>
+__device__ __forceinline__ int cen_slot(int e)
+{
+    const int q = e >> 1, odd = e & 1;
+    return 4 * q + ((CEN == 1) == (odd != 0) ? 0 : 2);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t cen_hamming(const CenRaw<K> &r, int slot)
+{
+    return (uint32_t)(__builtin_popcount(r.b[0] ^ r.m[slot]) + __builtin_popcount(r.b[1] ^ r.m[slot + 1]));
+}
+
+template <int K, int CEN>
+__device__ __forceinline__ uint32_t cen_cost(const CenRaw<K> &r, int e)
+{
+    int slot = cen_slot<K, CEN>(e);
+    if (CEN == 1 && (e & 1) == 0) {
+        // Moved load: its start offset was negative, i.e. row 0 and x - jK - e - 1 < 0.
+        if (r.row0 && r.lim < e + 1) slot -= 2;
+    }
+    const uint32_t c = cen_hamming<K>(r, slot);
+    return e <= r.lim ? c : (uint32_t)SF_CMAX;
+}
+
+// Census words -> interleaved u16 pairs: pair i = (e = i, e = K/2 + i).  Where
+// no lane of the wave has a match pixel outside the image (all but the first
+// D columns of a left base, the last D of a right base) the range tests are
+// skipped.
+template <int K, int CEN>
+__device__ __forceinline__ void unpack_cen(const CenRaw<K> &r, uint32_t (&c)[K / 2])
+{
+    if (__builtin_amdgcn_ballot_w64(r.lim < K - 1) == 0) {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i)
+            c[i] = cen_hamming<K>(r, cen_slot<K, CEN>(i)) | (cen_hamming<K>(r, cen_slot<K, CEN>(K / 2 + i)) << 16);
+    } else {
+#pragma unroll
+        for (int i = 0; i < K / 2; ++i) c[i] = cen_cost<K, CEN>(r, i) | (cen_cost<K, CEN>(r, K / 2 + i) << 16);
+    }
+}
+
 // Default prefetch depth (steps) of the cost stream of one chain.
 constexpr int SGM_U = 8;
+// Prefetch depth in census mode (each step holds 2 K + 3 registers).
+template <int K>
+constexpr int sgm_cen_u() { return K <= 8 ? 2 : 1; }
 
 // Walk chain l of direction r with the 16 lanes of this DPP row (lane j).
 // cost: [H][W][D]; slab: this direction's [H][W][D] u8 slab (ATOMIC == false)
 // or S [H][W][D] u16 (ATOMIC == true).
-template <int K, bool ATOMIC, int U = SGM_U, bool ADAPT = false, bool PACK = false>
+// CEN != 0: costs from the census words cen_b (base) and cen_m (match) instead
+// of the cost volume (unused then).
+template <int K, bool ATOMIC, int U = SGM_U, bool ADAPT = false, bool PACK = false, int CEN = 0>
 __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint8_t *__restrict__ slab,
                                           uint16_t *__restrict__ S, int H, int W, int P1, int P2,
                                           int r, int l, int j, const uint8_t *img = nullptr,
-                                          int pitch = 0)
+                                          int pitch = 0, const uint64_t *cen_b = nullptr,
+                                          const uint64_t *cen_m = nullptr)
 {
+    static_assert(CEN == 0 || (!ADAPT && !PACK), "census mode takes neither packed costs nor adaptive P2");
     constexpr int D = 16 * K;
     constexpr int NP = K / 2;
     constexpr int CPX = PACK ? 3 * D / 4 : D;  // cost bytes per pixel
@@ -348,6 +419,19 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
         SGM_RSRC_WORD3);
     uint32_t ild = ADAPT ? (uint32_t)(y * pitch + x) : 0u;
     const uint32_t istep = ADAPT ? (uint32_t)(ry * pitch + rx) : 0u;
+    // Census words (census mode): byte offsets of the base word and of the
+    // match word of e = 0 at the next fetched step.  Offsets left of a row's
+    // start or past the array wrap or run beyond the buffer, which reads zeros;
+    // those costs are replaced by SF_CMAX (lim) anyway.
+    const int cbytes = CEN ? (int)((size_t)H * W * 8) : 0;
+    const __amdgpu_buffer_rsrc_t rs_cb = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint64_t *>(CEN ? cen_b : nullptr), (short)0, cbytes, SGM_RSRC_WORD3);
+    const __amdgpu_buffer_rsrc_t rs_cm = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint64_t *>(CEN ? cen_m : nullptr), (short)0, cbytes, SGM_RSRC_WORD3);
+    const uint32_t cwstep = 8u * (uint32_t)(ry * W + rx);
+    uint32_t cbo = CEN ? 8u * (uint32_t)(y * W + x) : 0u;
+    uint32_t cmo = CEN ? 8u * (uint32_t)(y * W + x + (CEN == 1 ? -j * K : j * K)) : 0u;
+    int cx = x;
     const float fP2 = (float)P2;
     uint32_t prevI = 0;
 
@@ -364,15 +448,39 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     uint32_t below = SGM_SENT, above = SGM_SENT;
     // Steps past the end of this chain (other chains of the wave may be longer)
     // load whatever the buffer holds there (zeros beyond it) and store nothing.
-    using Raw = std::conditional_t<PACK, CostPk<PACK ? K : 8>, CostRaw<K>>;
+    using Raw = std::conditional_t<(CEN != 0), CenRaw<K>,
+                                   std::conditional_t<PACK, CostPk<PACK ? K : 8>, CostRaw<K>>>;
     auto fetch = [&](int t0, Raw(&buf)[U], uint32_t(&ib)[U]) {
         (void)t0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if constexpr (PACK)
+            if constexpr (CEN != 0) {
+                const u32x2 bw = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(rs_cb, (int)cbo, 0, 0));
+                buf[u].b[0] = bw.x;
+                buf[u].b[1] = bw.y;
+#pragma unroll
+                for (int q = 0; q < K / 2; ++q) {
+                    int o;
+                    if constexpr (CEN == 1)
+                        o = max((int)(cmo - 16u * (uint32_t)q - 8u), 0);  // moved load (see CenRaw)
+                    else
+                        o = (int)(cmo + 16u * (uint32_t)q);
+                    const u32x4 v = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs_cm, o, 0, 0));
+                    buf[u].m[4 * q + 0] = v.x;
+                    buf[u].m[4 * q + 1] = v.y;
+                    buf[u].m[4 * q + 2] = v.z;
+                    buf[u].m[4 * q + 3] = v.w;
+                }
+                buf[u].lim = CEN == 1 ? cx - j * K : W - 1 - cx - j * K;
+                buf[u].row0 = cbo < 8u * (uint32_t)W;
+                cbo += cwstep;
+                cmo += cwstep;
+                cx += rx;
+            } else if constexpr (PACK) {
                 load_pk_buf<K>(rs, ld, buf[u]);
-            else
+            } else {
                 load_raw_buf<K>(rs, ld, buf[u]);
+            }
             ld += (uint32_t)cstep;
             if constexpr (ADAPT) {
                 ib[u] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs_img, (int)ild, 0, 0);
@@ -384,7 +492,9 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
     };
     auto step = [&](int t, const Raw &raw, uint32_t inten) {
         uint32_t c[NP];
-        if constexpr (PACK)
+        if constexpr (CEN != 0)
+            unpack_cen<K, CEN>(raw, c);
+        else if constexpr (PACK)
             unpack_pk<K>(raw, j, c);
         else
             unpack<K>(raw, c);
@@ -463,15 +573,38 @@ __global__ __launch_bounds__(SGM_NT) void sgm_paths_kernel(const uint8_t *__rest
                                                            const uint8_t *__restrict__ img, int pitch)
 {
     constexpr int D = 16 * K;
-    const int g = blockIdx.x * SGM_CPB + (threadIdx.x >> 4);
-    const int j = threadIdx.x & 15;
-    if (g >= tab.off[tab.ndir]) return;
+    // The direction is uniform over the block (whole blocks per direction), so
+    // the slab's buffer resource stays in scalar registers.
+    const int g0 = blockIdx.x * SGM_CPB;
     int k = 0;
-    while (g >= tab.off[k + 1]) ++k;
+    while (g0 >= tab.off[k + 1]) ++k;
+    const int l = g0 - tab.off[k] + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (l >= tab.n[k]) return;
     const size_t npx = (size_t)H * W;
     uint8_t *sl = ATOMIC ? nullptr : slab + (size_t)k * npx * D;
-    sgm_chain<K, ATOMIC, SGM_U, ADAPT>(cost, sl, S, H, W, P1, P2, tab.dir[k], g - tab.off[k], j, img,
-                                       pitch);
+    sgm_chain<K, ATOMIC, SGM_U, ADAPT>(cost, sl, S, H, W, P1, P2, tab.dir[k], l, j, img, pitch);
+}
+
+// One view in census mode (CEN = 1 left base, 2 right base): no cost volume.
+template <int K, bool ATOMIC, int CEN>
+__global__ __launch_bounds__(SGM_NT) void sgm_paths_census_kernel(const uint64_t *__restrict__ cen_b,
+                                                                  const uint64_t *__restrict__ cen_m,
+                                                                  int H, int W, int P1, int P2,
+                                                                  PathTable tab, uint8_t *__restrict__ slab,
+                                                                  uint16_t *__restrict__ S)
+{
+    constexpr int D = 16 * K;
+    const int g0 = blockIdx.x * SGM_CPB;  // whole blocks per direction, as sgm_paths_kernel
+    int k = 0;
+    while (g0 >= tab.off[k + 1]) ++k;
+    const int l = g0 - tab.off[k] + (threadIdx.x >> 4);
+    const int j = threadIdx.x & 15;
+    if (l >= tab.n[k]) return;
+    const size_t npx = (size_t)H * W;
+    uint8_t *sl = ATOMIC ? nullptr : slab + (size_t)k * npx * D;
+    sgm_chain<K, ATOMIC, sgm_cen_u<K>(), false, false, CEN>(nullptr, sl, S, H, W, P1, P2, tab.dir[k], l, j,
+                                                            nullptr, 0, cen_b, cen_m);
 }
 
 // Many views from a task table (all tasks of one launch share K = D / 16).
@@ -575,6 +708,28 @@ static void launch_paths(bool atomic, int nblk, hipStream_t st, const uint8_t *c
         else
             hipLaunchKernelGGL((sgm_paths_kernel<K, false, false>), dim3(nblk), dim3(SGM_NT), 0, st,
                                cost, H, W, P1, P2, tab, slab, S, img, pitch);
+    }
+}
+
+template <int K>
+static void launch_paths_census(bool atomic, int right, int nblk, hipStream_t st, const uint64_t *cb,
+                                const uint64_t *cm, int H, int W, int P1, int P2, const PathTable &tab,
+                                uint8_t *slab, uint16_t *S)
+{
+    if (right) {
+        if (atomic)
+            hipLaunchKernelGGL((sgm_paths_census_kernel<K, true, 2>), dim3(nblk), dim3(SGM_NT), 0, st, cb, cm, H,
+                               W, P1, P2, tab, slab, S);
+        else
+            hipLaunchKernelGGL((sgm_paths_census_kernel<K, false, 2>), dim3(nblk), dim3(SGM_NT), 0, st, cb, cm, H,
+                               W, P1, P2, tab, slab, S);
+    } else {
+        if (atomic)
+            hipLaunchKernelGGL((sgm_paths_census_kernel<K, true, 1>), dim3(nblk), dim3(SGM_NT), 0, st, cb, cm, H,
+                               W, P1, P2, tab, slab, S);
+        else
+            hipLaunchKernelGGL((sgm_paths_census_kernel<K, false, 1>), dim3(nblk), dim3(SGM_NT), 0, st, cb, cm, H,
+                               W, P1, P2, tab, slab, S);
     }
 }
 
@@ -722,11 +877,13 @@ extern "C" size_t sf_sgm_workspace_bytes(int H, int W, int D)
     return (size_t)8 * H * W * D;
 }
 
+// cen_b != NULL: census mode (costs from cen_b / cen_m, base_is_right), cost unused.
 static int aggregate_impl(const uint8_t *cost, const uint8_t *img, int pitch, int H, int W, int D,
                           int P1, int P2, uint32_t path_mask, uint16_t *S, void *workspace,
-                          size_t ws_bytes, void *stream)
+                          size_t ws_bytes, void *stream, const uint64_t *cen_b = nullptr,
+                          const uint64_t *cen_m = nullptr, int base_is_right = 0)
 {
-    SF_REQUIRE(cost && S, SF_EINVAL, "sf_sgm_aggregate: NULL pointer");
+    SF_REQUIRE((cost || cen_b) && S, SF_EINVAL, "sf_sgm_aggregate: NULL pointer");
     SF_REQUIRE(H > 0 && W > 0, SF_EINVAL, "sf_sgm_aggregate: H and W must be positive");
     SF_REQUIRE(P1 >= 0 && P2 >= P1, SF_EINVAL, "sf_sgm_aggregate: need 0 <= P1 <= P2");
     SF_REQUIRE(P2 <= 8000, SF_EINVAL, "sf_sgm_aggregate: P2 > 8000 would overflow uint16 S");
@@ -743,7 +900,8 @@ static int aggregate_impl(const uint8_t *cost, const uint8_t *img, int pitch, in
     for (int r = 0; r < 8; ++r) {
         if (!(path_mask & (1u << r))) continue;
         tab.dir[tab.ndir] = r;
-        tab.off[tab.ndir + 1] = tab.off[tab.ndir] + chains_of(r, H, W);
+        tab.n[tab.ndir] = chains_of(r, H, W);
+        tab.off[tab.ndir + 1] = tab.off[tab.ndir] + (tab.n[tab.ndir] + SGM_CPB - 1) / SGM_CPB * SGM_CPB;
         ++tab.ndir;
     }
     const size_t ncell = (size_t)H * W * D;
@@ -763,9 +921,20 @@ static int aggregate_impl(const uint8_t *cost, const uint8_t *img, int pitch, in
         int rc = launch_status("fill_u32_kernel");
         if (rc) return rc;
     }
-    const int nchains = tab.off[tab.ndir];
-    const int nblk = (nchains + SGM_CPB - 1) / SGM_CPB;
-    {
+    const int nblk = tab.off[tab.ndir] / SGM_CPB;
+    if (cen_b) {
+        ProfScope prof("sgm_paths", st);
+        switch (D / 16) {
+#define SF_CEN_CASE(KK)                                                                                  \
+    case KK:                                                                                             \
+        launch_paths_census<KK>(atomic, base_is_right, nblk, st, cen_b, cen_m, H, W, P1, P2, tab, slab, S); \
+        break;
+            SF_CEN_CASE(2) SF_CEN_CASE(4) SF_CEN_CASE(6) SF_CEN_CASE(8) SF_CEN_CASE(10) SF_CEN_CASE(12)
+            SF_CEN_CASE(14) SF_CEN_CASE(16)
+#undef SF_CEN_CASE
+        default: return fail(SF_EUNSUPPORTED, "sf_sgm_aggregate_census: unsupported D");
+        }
+    } else {
         ProfScope prof("sgm_paths", st);
         switch (D / 16) {
         case 2: launch_paths<2>(atomic, nblk, st, cost, H, W, P1, P2, tab, slab, S, img, pitch); break;
@@ -804,6 +973,18 @@ extern "C" int sf_sgm_aggregate(const uint8_t *cost, int H, int W, int D, int P1
 {
     clear_error();
     return aggregate_impl(cost, nullptr, 0, H, W, D, P1, P2, path_mask, S, workspace, ws_bytes, stream);
+}
+
+extern "C" int sf_sgm_aggregate_census(const uint64_t *cen_base, const uint64_t *cen_match, int H, int W,
+                                       int D, int base_is_right, int P1, int P2, uint32_t path_mask,
+                                       uint16_t *S, void *workspace, size_t ws_bytes, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(cen_base && cen_match, SF_EINVAL, "sf_sgm_aggregate_census: NULL census");
+    SF_REQUIRE(base_is_right == 0 || base_is_right == 1, SF_EINVAL,
+               "sf_sgm_aggregate_census: base_is_right must be 0 or 1");
+    return aggregate_impl(nullptr, nullptr, 0, H, W, D, P1, P2, path_mask, S, workspace, ws_bytes, stream,
+                          cen_base, cen_match, base_is_right);
 }
 
 extern "C" int sf_sgm_aggregate_adaptive(const uint8_t *cost, const uint8_t *img, int pitch, int H,

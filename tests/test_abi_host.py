@@ -125,6 +125,20 @@ def test_variant_validation(L):
     expect(L.sf_frame_plan_create(64, 64, 32, 10, 120, 1, 64, None, ct.byref(plan)), 1, "unknown flags")
 
 
+def test_aggregate_census_validation(L):
+    ws = 1 << 20
+    f = L.sf_sgm_aggregate_census
+    expect(f(None, FAKE, 4, 4, 32, 0, 10, 120, 255, FAKE, FAKE, ws, None), 1, "NULL census")
+    expect(f(FAKE, None, 4, 4, 32, 0, 10, 120, 255, FAKE, FAKE, ws, None), 1, "NULL census")
+    expect(f(FAKE, FAKE, 4, 4, 32, 2, 10, 120, 255, FAKE, FAKE, ws, None), 1, "base_is_right")
+    expect(f(FAKE, FAKE, 4, 4, 32, 0, 20, 10, 255, FAKE, FAKE, ws, None), 1, "P1 <= P2")
+    expect(f(FAKE, FAKE, 4, 4, 32, 1, 10, 120, 0, FAKE, FAKE, ws, None), 1, "path_mask")
+    expect(f(FAKE, FAKE, 4, 4, 48, 0, 10, 120, 255, FAKE, FAKE, ws, None), 2, "multiple of 32")
+    expect(f(FAKE, FAKE, 4, 4, 32, 0, 10, 120, 255, FAKE, FAKE, 100, None), 4, "workspace")
+    expect(f(FAKE, FAKE, 4, 4, 32, 0, 10, 120, 255, None, FAKE, ws, None), 1, "NULL")
+    expect(f(FAKE, FAKE, 8192, 1024, 256, 0, 10, 120, 255, FAKE, FAKE, 1 << 40, None), 1, "2^31")
+
+
 def test_volume_offset_limit(L):
     # H * W * D must stay below 2^31 for the 32-bit volume offsets of the kernels.
     plan = ct.c_void_p()
