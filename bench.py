@@ -287,11 +287,18 @@ def bench_batch(args, dev):
 
     steps = max(1, min(args.steps, 10))
     ms_batch, b = time_graph(pairs, steps, max(1, args.warmup))
+    nwaves = b.nwaves
+    # Free the whole batch's workspace (up to the budget) before the per-class
+    # batches take theirs; the parity spot check below builds it again.
+    del b
+    torch.cuda.empty_cache()
     cells = lambda prs: sum(p["left"].shape[0] * p["left"].shape[1] * p["D"] * 8 for p in prs)  # noqa: E731
     per_class = {}
     for (H, W, D) in classes:
         prs = [p for p in pairs if (p["left"].shape[0], p["left"].shape[1], p["D"]) == (H, W, D)]
-        ms_c, _ = time_graph(prs, steps, 1)
+        ms_c, bc = time_graph(prs, steps, 1)
+        del bc
+        torch.cuda.empty_cache()
         per_class[f"{W}x{H}xD{D}"] = {"pairs": len(prs), "ms": ms_c,
                                      "gcups_delivered": cells(prs) / (ms_c * 1e-3) / 1e9,
                                      "gcups_all_passes": 2 * cells(prs) / (ms_c * 1e-3) / 1e9}
@@ -325,6 +332,9 @@ def bench_batch(args, dev):
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1)
     # Spot parity: the last pair of each class, batched vs one-by-one.
+    bufs.clear()
+    torch.cuda.empty_cache()
+    b = batch.Batch(pairs, tunings=tunings, mem_budget=budget, device=dev)
     b.run()
     torch.cuda.synchronize()
     same = True
@@ -342,7 +352,7 @@ def bench_batch(args, dev):
         "data": "synthetic (seeded piecewise-planar pairs)",
         "config": {"workload": f"{args.pairs} uneven stereo pairs: 640x480 D=64, 1242x375 D=128, "
                                "1920x1080 D=256 (pair i has class i mod 3), one HIP graph",
-                   "mem_budget_gb": args.mem_budget_gb, "waves": b.nwaves},
+                   "mem_budget_gb": args.mem_budget_gb, "waves": nwaves},
         "batch_latency_ms": ms_batch, "per_class": per_class, "autotune": tune_info,
         "plain_one_by_one_ms": ms_plain, "speedup_batched_vs_plain": ms_plain / ms_batch,
         "spot_parity_batched_equals_one_by_one": same,
