@@ -178,6 +178,44 @@ def bench_tuning_sweep(args, dev):
                       "copies": 3}), flush=True)
 
 
+def sceneflow_diagnostics(fr, valid0, valid1, valid):
+    """Density of the scene flow over all pixels and over non-occluded ones,
+    and why the other pixels are undefined, in the order the combination rule
+    tests them: the flow leaves the image, the t0 disparity was rejected, or a
+    t1 disparity tap was rejected.  Non-occluded: visible in the t0 right view,
+    moved (by the generator's flow) to a pixel inside the image that is visible
+    in the t1 right view.  Host-side, from one frame's outputs."""
+    import numpy as np
+
+    H, W = valid0.shape
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float32)
+    u, v = fr.flow[..., 0], fr.flow[..., 1]
+    xp, yp = xs + u, ys + v
+    inside = (xp >= 0) & (xp <= W - 1) & (yp >= 0) & (yp <= H - 1)
+    x0 = np.clip(np.floor(np.where(inside, xp, 0)), 0, W - 1).astype(np.int64)
+    y0 = np.clip(np.floor(np.where(inside, yp, 0)), 0, H - 1).astype(np.int64)
+    x1, y1 = np.minimum(x0 + 1, W - 1), np.minimum(y0 + 1, H - 1)
+    v1 = valid1.astype(bool)
+    taps = v1[y0, x0] & v1[y0, x1] & v1[y1, x0] & v1[y1, x1]
+    d0 = valid0.astype(bool)
+    defined = (valid & 1).astype(bool)
+    out_img = ~inside
+    bad_d0 = inside & ~d0
+    bad_d1 = inside & d0 & ~taps
+    gu, gv = fr.gt_flow[..., 0], fr.gt_flow[..., 1]
+    gx, gy = np.rint(xs + gu), np.rint(ys + gv)
+    gin = (gx >= 0) & (gx <= W - 1) & (gy >= 0) & (gy <= H - 1)
+    gxi = np.clip(gx, 0, W - 1).astype(np.int64)
+    gyi = np.clip(gy, 0, H - 1).astype(np.int64)
+    noc = ~fr.t0.occluded & gin & ~fr.t1.occluded[gyi, gxi]
+    n = float(H * W)
+    return {"sceneflow_density_noc": float(defined[noc].mean()), "noc_fraction": float(noc.mean()),
+            "undefined_flow_leaves_image": float(out_img.sum() / n),
+            "undefined_t0_disparity_rejected": float(bad_d0.sum() / n),
+            "undefined_t1_disparity_rejected": float(bad_d1.sum() / n),
+            "rule_matches_kernel": bool(np.array_equal(defined, inside & d0 & taps))}
+
+
 def cpu_baseline(fr, D, runs=3):
     """The oracle on one stereo pair of the frame, timed `runs` times on one
     host thread; the median run gives the rate."""
@@ -1061,6 +1099,8 @@ def main():
         v0t, vt = res_run["valid0"], res_run["valid"]
     valid0 = float(v0t.float().mean().item())
     dens = float((vt & 1).float().mean().item())
+    v1t = res_run[1]["valid"] if args.pipeline == "stages" else res_run["valid1"]
+    diag = sceneflow_diagnostics(fr, v0t.cpu().numpy(), v1t.cpu().numpy(), vt.cpu().numpy())
     res = {
         "metric": METRIC,
         "value": gcups_delivered,
@@ -1083,6 +1123,7 @@ def main():
         "gcups_all_passes": gcups_passes,
         "lr_valid_frac_t0": valid0,
         "sceneflow_density": dens,
+        "sceneflow_diagnostics": diag,
         "kernels": breakdown,
         "roofline": roofline,
     }
