@@ -407,6 +407,26 @@ int sf_prof_disable(void);
 int sf_prof_query(const char *kernel, double *total_ms, int *launches);
 
 /* ---------------------------------------------------------------------------
+ * Checked builds (libsf_checked.so: the same library built with index checks).
+ * At the accesses whose indices come from data (bilinear taps at x + F(x), the
+ * LR check's d*_R(x - d*), flow candidates, densification sources, the
+ * temporal check's chained pixel, each chain step's cost and slab bytes) a
+ * failed check sets one bit per site in device memory; the access proceeds as
+ * in the normal build and nothing traps.
+ *   sf_debug_checked: 1 for a checked build, 0 otherwise.
+ *   sf_debug_check: waits for the device, then *bits = the sites whose checks
+ *     failed since the last clear on the current device (bit 0 taps, 1
+ *     temporal, 2 LR check, 3 flow samples, 4 densification, 5 chain costs,
+ *     6 chain slabs, 31 self-test); clear != 0 resets them.  0 in a normal
+ *     build.  Errors: SF_EINVAL (NULL), SF_EHIP.
+ *   sf_debug_selftest: enqueues a kernel that checks i < n for i = 0 .. n and
+ *     reads no memory, so a checked build records bit 31.  Errors: SF_EINVAL
+ *     (n outside [0, 2^24)), SF_EHIP. */
+int sf_debug_checked(void);
+int sf_debug_check(uint32_t *bits, int clear);
+int sf_debug_selftest(int n, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Densification of the sparse scene-flow map (the paper reports a dense
  * version interpolated by the benchmark and names a better interpolation as
  * future work, Sec. 4; the fill rule is this library's own):

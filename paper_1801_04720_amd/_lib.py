@@ -53,6 +53,9 @@ SIGNATURES = {
     "sf_sgm_aggregate": (I, [P, I, I, I, I, I, U32, P, P, SZ, P]),
     "sf_sgm_set_epilogue": (I, [I]),
     "sf_sgm_aggregate_census": (I, [P, P, I, I, I, I, I, I, U32, P, P, SZ, P]),
+    "sf_debug_checked": (I, []),
+    "sf_debug_check": (I, [ct.POINTER(ct.c_uint32), I]),
+    "sf_debug_selftest": (I, [I, P]),
     "sf_wta_lr": (I, [P, P, P, I, I, I, I, I, I, P, P, P, P, P, P]),
     "sf_combine": (I, [P, P, P, P, P, I, I, ct.POINTER(SfCamera), P, P, P, P, P]),
     "sf_plan_workspace_bytes": (SZ, [P]),

@@ -17,6 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsf.so")
+# The same library with the kernels' index checks compiled in (sf_check.hpp).
+LIB_CHECKED = os.path.join(PKG, "libsf_checked.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -49,16 +51,23 @@ def _compile(src: str, build_dir: str = BUILD, extra=()) -> str:
     return obj
 
 
-def build(jobs: int = 8, sanitize: bool = False, out: str | None = None, build_dir: str | None = None) -> str:
+def build(jobs: int = 8, sanitize: bool = False, out: str | None = None, build_dir: str | None = None,
+          checked: bool = False) -> str:
     """Compile every HIP source and link libsf.so; returns its path.  With
     sanitize=True the host code is instrumented (SANITIZE) and the library goes
-    to `out` (default: a separate build folder), never over the product build."""
-    lib = out or (os.path.join(BUILD + "_sanitize", "libsf.so") if sanitize else LIB)
-    bdir = build_dir or (BUILD + "_sanitize" if sanitize else BUILD)
+    to `out` (default: a separate build folder), never over the product build.
+    checked=True compiles the kernels' index checks in (-DSF_CHECKED) and links
+    libsf_checked.so next to libsf.so."""
+    if checked:
+        lib = out or LIB_CHECKED
+        bdir = build_dir or BUILD + "_checked"
+    else:
+        lib = out or (os.path.join(BUILD + "_sanitize", "libsf.so") if sanitize else LIB)
+        bdir = build_dir or (BUILD + "_sanitize" if sanitize else BUILD)
     os.makedirs(bdir, exist_ok=True)
     os.makedirs(os.path.dirname(lib), exist_ok=True)
     srcs = sources()
-    extra = SANITIZE if sanitize else []
+    extra = (SANITIZE if sanitize else []) + (["-DSF_CHECKED"] if checked else [])
     with cf.ThreadPoolExecutor(max_workers=min(jobs, len(srcs))) as ex:
         objs = list(ex.map(lambda f: _compile(f, bdir, extra), srcs))
     tmp = lib + ".tmp%d" % os.getpid()

@@ -106,3 +106,60 @@ extern "C" int sf_prof_query(const char *kernel, double *total_ms, int *launches
 extern "C" int sf_abi_version(void) { return SF_ABI_VERSION; }
 
 extern "C" const char *sf_last_error(void) { return sf::g_err; }
+
+// --- checked builds --------------------------------------------------------
+#include "sf_check.hpp"
+
+SF_CHECK_TU(abi)
+
+namespace sf {
+
+// Checks i < n for i = 0 .. n (one thread each) and touches no memory, so in a
+// checked build the thread i = n records CHK_SELFTEST.
+__global__ void check_selftest_kernel(int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    SF_BOUNDS(i < n, CHK_SELFTEST);
+}
+
+}  // namespace sf
+
+using namespace sf;
+
+extern "C" int sf_debug_checked(void)
+{
+#ifdef SF_CHECKED
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+extern "C" int sf_debug_selftest(int n, void *stream)
+{
+    clear_error();
+    SF_REQUIRE(n >= 0 && n < (1 << 24), SF_EINVAL, "sf_debug_selftest: n must be in [0, 2^24)");
+    hipLaunchKernelGGL(check_selftest_kernel, dim3((n + 256) / 256), dim3(256), 0, as_stream(stream), n);
+    return launch_status("check_selftest_kernel");
+}
+
+extern "C" int sf_debug_check(uint32_t *bits, int clear)
+{
+    clear_error();
+    SF_REQUIRE(bits, SF_EINVAL, "sf_debug_check: NULL pointer");
+    *bits = 0;
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        set_error("sf_debug_check: %s", hipGetErrorString(e));
+        return SF_EHIP;
+    }
+    int (*const readers[])(uint32_t *, bool) = {check_read_combine, check_read_wta, check_read_flow,
+                                                check_read_densify, check_read_sgm, check_read_abi};
+    for (auto rd : readers)
+        if (rd(bits, clear != 0)) {
+            set_error("sf_debug_check: reading a check word failed");
+            return SF_EHIP;
+        }
+    return SF_OK;
+}

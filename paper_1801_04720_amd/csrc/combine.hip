@@ -4,8 +4,11 @@
 // the camera).  One thread per pixel; flow and outputs are read / written as
 // float2 / float4 / 3 x float, coalesced along rows.  Built without FMA
 // contraction so every product and sum is the FP32 operation stated.
+#include "sf_check.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
+
+SF_CHECK_TU(combine)
 
 namespace sf {
 
@@ -30,6 +33,7 @@ __global__ __launch_bounds__(256) void combine_kernel(
         const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
         const size_t i00 = (size_t)y0 * W + x0, i10 = (size_t)y0 * W + x1;
         const size_t i01 = (size_t)y1 * W + x0, i11 = (size_t)y1 * W + x1;
+        SF_BOUNDS(x0 >= 0 && y0 >= 0 && x1 < W && y1 < H && x0 <= x1 && y0 <= y1, CHK_COMBINE_TAP);
         if (valid1[i00] && valid1[i10] && valid1[i01] && valid1[i11]) {
             const float fx = xp - (float)x0;
             const float fy = yp - (float)y0;
@@ -97,6 +101,7 @@ __global__ __launch_bounds__(256) void temporal_check_kernel(const float4 *__res
         const float yq = floorf(__fadd_rn((float)y, s.y) + 0.5f);
         if (xq >= 0.0f && xq <= (float)(W - 1) && yq >= 0.0f && yq <= (float)(H - 1)) {
             const size_t j = (size_t)yq * W + (size_t)xq;
+            SF_BOUNDS(j < (size_t)H * W, CHK_TEMPORAL);
             if (vb[j] & 1) {
                 const float4 t = b[j];
                 const float ca = s.w - s.z, cb = t.w - t.z;

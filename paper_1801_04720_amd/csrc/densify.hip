@@ -10,7 +10,10 @@
 // first / last defined pixel, the block combines the segments, and the
 // nearest-left / nearest-right index of every pixel lands in LDS.  Copy pass:
 // one block per empty row.
+#include "sf_check.hpp"
 #include "sf_internal.hpp"
+
+SF_CHECK_TU(densify)
 
 namespace sf {
 
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(DN_NT) void densify_rows_kernel(const float4 *__res
                 src = (sf4[row + xr].z < sf4[row + xl].z) ? xr : xl;
             else
                 src = xl >= 0 ? xl : xr;
+            SF_BOUNDS(src >= 0 && src < W, CHK_DENSIFY);
             v = sf4[row + src];
             f = 2;
         }
@@ -92,6 +96,7 @@ __global__ __launch_bounds__(DN_NT) void densify_copy_rows_kernel(const uint8_t 
             src = y + dy;
     }
     if (src < 0) return;  // nothing defined anywhere: the row pass left NaN / 0
+    SF_BOUNDS(src < H, CHK_DENSIFY);
     for (int x = threadIdx.x; x < W; x += DN_NT) {
         out[(size_t)y * W + x] = out[(size_t)src * W + x];
         fill[(size_t)y * W + x] = 3;

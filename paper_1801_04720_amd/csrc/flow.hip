@@ -23,8 +23,11 @@
 //     both components (B from the second image to the first, seed ^ 0x5bd1e995).
 // All integer: results are reproducible bit for bit.  One thread per pixel,
 // 16x16 blocks; the census words of both images come through L1/L2.
+#include "sf_check.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
+
+SF_CHECK_TU(flow)
 
 namespace sf {
 
@@ -71,6 +74,7 @@ __device__ __forceinline__ int flow_cost(const uint64_t (&a)[9], const uint64_t 
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         const size_t row = (size_t)min(max(ty + 2 * j - 2, 0), H - 1) * W;
+        SF_BOUNDS(row < (size_t)H * W && tx >= 0 && tx < W, CHK_FLOW_SAMPLE);
 #pragma unroll
         for (int i = 0; i < 3; ++i) s += __popcll(a[3 * j + i] ^ c1[row + min(max(tx + 2 * i - 2, 0), W - 1)]);
     }

@@ -36,8 +36,11 @@
 //     chosen per task; optionally persistent, pulling tasks from a counter.
 #include <type_traits>
 
+#include "sf_check.hpp"
 #include "sf_internal.hpp"
 #include "sgm_tasks.hpp"
+
+SF_CHECK_TU(sgm)
 
 namespace sf {
 
@@ -477,8 +480,10 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
                 cmo += cwstep;
                 cx += rx;
             } else if constexpr (PACK) {
+                if (t0 + u < len) SF_BOUNDS((size_t)ld + (K == 8 ? 8 : 12) <= (size_t)H * W * CPX, CHK_SGM_COST);
                 load_pk_buf<K>(rs, ld, buf[u]);
             } else {
+                if (t0 + u < len) SF_BOUNDS((size_t)ld + K <= (size_t)H * W * CPX, CHK_SGM_COST);
                 load_raw_buf<K>(rs, ld, buf[u]);
             }
             ld += (uint32_t)cstep;
@@ -535,10 +540,13 @@ __device__ __forceinline__ void sgm_chain(const uint8_t *__restrict__ cost, uint
 #pragma unroll
         for (int i = 0; i < NP; ++i) L[i] = nL[i];
         if (t < len) {
-            if constexpr (ATOMIC)
+            if constexpr (ATOMIC) {
+                SF_BOUNDS((size_t)(stS - S) + K <= (size_t)H * W * D, CHK_SGM_SLAB);
                 emit<K, true>(L, nullptr, stS);
-            else
+            } else {
+                SF_BOUNDS((size_t)st + K <= (size_t)H * W * D, CHK_SGM_SLAB);
                 emit_buf<K>(L, rs_out, st);
+            }
         }
         if constexpr (ATOMIC)
             stS += bstep;

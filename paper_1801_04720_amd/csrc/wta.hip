@@ -11,8 +11,11 @@
 // right map, left map with or without the LR check, with or without the
 // network features), and wta_diag_slab_kernel adds the diagonal-search right
 // map.
+#include "sf_check.hpp"
 #include "sf_internal.hpp"
 #include "stages.hpp"
+
+SF_CHECK_TU(wta)
 
 namespace sf {
 
@@ -89,6 +92,7 @@ __global__ __launch_bounds__(WTA_NT) void wta_left_kernel(
         const int q = x - ds;
         ok = 0;
         if (q >= 0) {
+            SF_BOUNDS(q < W && y < H, CHK_WTA_LR);
             int diff = ds - (int)wta_r[(size_t)y * W + q];
             diff = diff < 0 ? -diff : diff;
             ok = diff <= tol;
@@ -391,7 +395,10 @@ __global__ __launch_bounds__(WTA_NT) void wta_slab_kernel(WtaArgs a)
         const bool live = px0 + g * WTA_PPB < npx;
         const int y = live ? cy : v.H - 1, x = live ? cx : v.W - 1;
         int rq = 0;
-        if constexpr (wm_lr(MODE)) rq = v.wta_r[(size_t)y * v.W + max(x - r.ds, 0)];
+        if constexpr (wm_lr(MODE)) {
+            SF_BOUNDS(x - r.ds < v.W && y < v.H && y >= 0, CHK_WTA_LR);
+            rq = v.wta_r[(size_t)y * v.W + max(x - r.ds, 0)];
+        }
         if (g > 0 && px0 + (g - 1) * WTA_PPB < npx)
             wta_finish<K, MODE>(v, prev, prev_px, prev_x, j, prev_rq, prev_in);
         prev = r;
@@ -597,6 +604,7 @@ __global__ __launch_bounds__(256) void lr_check_kernel(const int16_t *__restrict
     const int dl = wl[px], q = x - dl;
     int ok = 0;
     if (q >= 0) {
+        SF_BOUNDS(q < W, CHK_WTA_LR);
         int diff = dl - (int)wr[(size_t)y * W + q];
         diff = diff < 0 ? -diff : diff;
         ok = diff <= tol;

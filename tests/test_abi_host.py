@@ -174,3 +174,16 @@ def test_network_and_judge_validation(L):
     expect(L.sf_lrnet_forward_noalloc(None, FAKE, 1, 4, 4, FAKE, None), 1, "NULL")
     expect(L.sf_lrnet_forward_noalloc(FAKE, FAKE, 1, 0, 4, FAKE, None), 1, "positive")
     expect(L.sf_lrnet_forward_noalloc(FAKE, FAKE, 70000, 4, 4, FAKE, None), 1, "too large")
+
+
+def test_checked_build_flags(L):
+    import ctypes
+
+    assert L.sf_debug_checked() == 0
+    expect(L.sf_debug_check(None, 0), 1, "NULL")
+    expect(L.sf_debug_selftest(-1, None), 1, "n must")
+    path = os.path.join(ROOT, "paper_1801_04720_amd", "libsf_checked.so")
+    if not os.path.exists(path):
+        pytest.fail("libsf_checked.so is not built (run __graft_entry__.build())")
+    C = ctypes.CDLL(path)
+    assert C.sf_debug_checked() == 1
