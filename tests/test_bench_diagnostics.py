@@ -5,7 +5,6 @@ combination rule they restate gives the oracle's validity mask."""
 import os
 import sys
 
-import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
