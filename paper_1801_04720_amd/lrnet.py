@@ -4,7 +4,6 @@ Marshalling only: forward, loss/gradient and the Adam step are HIP kernels of
 libsf.so (sf_lrnet_forward / sf_lrnet_grad / sf_lrnet_backward / sf_lrnet_adam)."""
 from __future__ import annotations
 
-
 import numpy as np
 import torch
 
